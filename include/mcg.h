@@ -1,0 +1,230 @@
+/*
+ * mcg.h -- C ABI of the gfx950 (MI355X) library for stout-preconditioned
+ * Maximal Center Gauge fixing in SU(3) (O Cais et al., arXiv:0807.0264).
+ *
+ * The calls follow the paper's statement of the method:
+ *   smear(U, rho, eps, n)        Sec. II.B and Sec. III (stout, over-improved stout)
+ *   mcg_fix(U) -> (G, R)         Sec. II.A (maximise V_U[G] by local updates)
+ *   apply_gauge(U, G)            Sec. II.A/B (U^G; preconditioning transform)
+ *   center_project(U, G) -> Z    Sec. II.A (nearest centre element of tr U^G)
+ *   count_vortices(Z)            Sec. II.A (non-trivial plaquettes of Z)
+ *
+ * Conventions
+ *   - Extents L = (Lx, Ly, Lz, Lt), each even and >= 2, periodic; site index
+ *     i = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2; half index
+ *     h = i >> 1 (the site's index among the V/2 sites of its parity).
+ *   - Gauge transform: U^G_mu(x) = G(x) U_mu(x) G(x+mu)^dagger.
+ *   - Functional: R = V_U = (1/(9 N_l)) sum_{x,mu} |tr U_mu(x)|^2, N_l = 4V.
+ *   - Centre phase: m in {-1,0,1} maximising Re(t e^{-2 pi i m/3}) with
+ *     t = tr U^G_mu(x) evaluated in FP64; candidates tried in the order
+ *     0, +1, -1 (first wins a tie); t = 0 gives m = 0.
+ *
+ * Memory (all device pointers, caller-owned, never freed by the library)
+ *   mcg_field  links in the internal structure-of-arrays layout: complex
+ *              element (mu, parity, k = 3*row + col, h) at complex offset
+ *              ((mu*2 + parity)*9 + k)*(V/2) + h; each complex is two reals
+ *              (re, im) of the field's precision (MCG_F64: double,
+ *              MCG_F32: float).  Size: mcg_field_bytes().
+ *   mcg_gauge  per-site SU(3) transform, always FP64: complex element
+ *              (parity, k, h) at complex offset (parity*9 + k)*(V/2) + h.
+ *              Size: mcg_gauge_bytes().
+ *   Z          int8 centre integers, element (mu, i) at mu*V + i.
+ *   Interchange arrays (mcg_pack_* / mcg_unpack_*): complex [Lt][Lz][Ly][Lx][4][3][3]
+ *              (links) or [Lt][Lz][Ly][Lx][3][3] (gauge), row-major 3x3.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls enqueue
+ * work on it and return without waiting, except those that return host
+ * scalars (functional, plaquette, theta, fix, fix_batch, center_project's
+ * min_margin, count_vortices, the backward's scalars), which synchronise
+ * that stream before returning.
+ *
+ * Errors: every call returns an mcg_status.  Negative values are errors
+ * (outputs undefined, the context stays usable); MCG_WNOTCONV is a warning
+ * with valid outputs.  mcg_last_error() gives the message of the context's
+ * last error.  No call aborts the process.
+ *
+ * Threads: a context may be used by one host thread at a time.  Calls on
+ * one context that overlap on the GPU (different streams) share the
+ * context's scratch buffers and race; use one context per stream.
+ */
+#ifndef MCG_H
+#define MCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcg_status;
+enum {
+  MCG_OK = 0,
+  MCG_WNOTCONV = 1, /* max_sweeps reached; G and R valid and resumable */
+  MCG_EINVAL = -1,  /* bad argument: odd/small extent, null pointer, dims mismatch, aliasing */
+  MCG_ENOMEM = -2,  /* scratch allocation failed */
+  MCG_EHIP = -3,    /* a HIP runtime call failed */
+  MCG_EINPUT = -4   /* input outside the method's range (e.g. smearing step too large) */
+};
+
+enum { MCG_F64 = 0, MCG_F32 = 1 };
+
+typedef struct {
+  int32_t L[4]; /* Lx (fastest), Ly, Lz, Lt */
+} mcg_dims;
+
+typedef struct {
+  mcg_dims d;
+  int32_t prec; /* MCG_F64 or MCG_F32 */
+  int32_t pad_;
+  void *ptr;    /* device, mcg_field_bytes(d, prec) bytes */
+} mcg_field;
+
+typedef struct {
+  mcg_dims d;
+  double *ptr; /* device, mcg_gauge_bytes(d) bytes */
+} mcg_gauge;
+
+/* Options of the fixing iteration (Sec. II.A; readings in the comments).
+ * A sweep is one update of every even site followed by one of every odd
+ * site ("iteration" of the paper; it counts work in blocks of 50). */
+typedef struct {
+  double tol;            /* stop after the first sweep s with R_s - R_{s-1} < tol */
+  double omega;          /* over-relaxation of each SU(2) subgroup step, in [0, 2] */
+  int32_t max_sweeps;    /* sweeps allowed in this call (>= 0) */
+  int32_t reunit_every;  /* re-unitarise G and re-derive W = U^G before every sweep s
+                            with (s-1) % reunit_every == 0, except the first of a call */
+  int32_t start_sweep;   /* global number of sweeps already done (resume) */
+  int32_t check_every;   /* host polls the device stop flag every this many sweeps (>= 1) */
+  double *traj;          /* nullable HOST array of max_sweeps+1 doubles: R before the
+                            first sweep and after each sweep done */
+} mcg_fix_opts;
+
+typedef struct {
+  double R;        /* R(U^G) after the final re-unitarisation of G */
+  double dR;       /* last R_s - R_{s-1} */
+  double theta;    /* stationarity residual (1/V) sum_x |TA X(x)|_F^2, X the local
+                      linearisation sum_k conj(tr M_k) M_k over the 8 links at x */
+  int32_t sweeps;  /* sweeps done in this call */
+  int32_t blocks50;/* ceil(sweeps / 50) */
+  int32_t status;  /* MCG_OK or MCG_WNOTCONV */
+  int32_t pad_;
+} mcg_fix_result;
+
+typedef struct mcg_ctx mcg_ctx;
+
+/* ---- context ------------------------------------------------------------ */
+/* Create a context on HIP device `device`; it owns scratch buffers, graphs
+ * and the autotune table.  Returns MCG_EHIP if the device is unusable. */
+mcg_status mcg_create(mcg_ctx **ctx, int32_t device);
+mcg_status mcg_destroy(mcg_ctx *ctx);
+const char *mcg_status_string(mcg_status s);
+const char *mcg_last_error(const mcg_ctx *ctx);
+
+/* Bytes of an internal link field / gauge field; 0 for invalid dims. */
+size_t mcg_field_bytes(mcg_dims d, int32_t prec);
+size_t mcg_gauge_bytes(mcg_dims d);
+
+/* ---- layout conversion ---------------------------------------------------- */
+/* src: device interchange links of precision src_prec -> dst (any precision;
+ * FP64 -> FP32 rounds to nearest). */
+mcg_status mcg_pack_links(mcg_ctx *ctx, const void *src, int32_t src_prec,
+                          mcg_field *dst, void *stream);
+mcg_status mcg_unpack_links(mcg_ctx *ctx, const mcg_field *src, void *dst,
+                            int32_t dst_prec, void *stream);
+/* src/dst: device interchange gauge field, complex double */
+mcg_status mcg_pack_gauge(mcg_ctx *ctx, const double *src, mcg_gauge *dst, void *stream);
+mcg_status mcg_unpack_gauge(mcg_ctx *ctx, const mcg_gauge *src, double *dst, void *stream);
+/* G(x) = 1 everywhere */
+mcg_status mcg_gauge_identity(mcg_ctx *ctx, mcg_gauge *G, void *stream);
+/* Re-unitarise every G(x) (Gram-Schmidt on rows, third row conj(r0 x r1)). */
+mcg_status mcg_gauge_reunit(mcg_ctx *ctx, mcg_gauge *G, void *stream);
+
+/* ---- smearing (Sec. II.B; parameters of Sec. III) -------------------------- */
+/* n Jacobi steps U' = exp(TA(C U^dagger)) U with the staple sum
+ *   C = rho sum_{nu != mu} [ (5-2eps)/3 (2 plaquette staples)
+ *                          - (1-eps)/12 (6 rectangle staples) ]
+ * (eps = 1: stout; eps < 1: over-improved stout).  TA(M) is the traceless
+ * anti-Hermitian part.  n == 0 copies U.  U and out must have equal dims and
+ * precision and must not alias.  MCG_EINPUT if some exponent is too large for
+ * the series used (spectral radius of C U^dagger above 6). */
+mcg_status mcg_smear(mcg_ctx *ctx, const mcg_field *U, mcg_field *out, double rho,
+                     double eps, int32_t n, void *stream);
+
+/* ---- gauge transform and functional (Sec. II.A) ------------------------------- */
+/* out = U^G (same precision as U; computed in FP64, rounded once). out may alias U. */
+mcg_status mcg_apply_gauge(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G,
+                           mcg_field *out, void *stream);
+/* *R = V_U[1] of the field as given (host scalar; FP64 accumulation). */
+mcg_status mcg_functional(mcg_ctx *ctx, const mcg_field *U, double *R, void *stream);
+/* *P = (1/(18V)) sum_{x, mu<nu} Re tr U_P (host scalar), a gauge invariant. */
+mcg_status mcg_plaquette(mcg_ctx *ctx, const mcg_field *U, double *P, void *stream);
+/* *theta = stationarity residual of the field as given (host scalar). */
+mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stream);
+
+/* ---- MCG fixing (Sec. II.A; preconditioning of Sec. II.B) ---------------------- */
+/* One half-sweep in place: every site x of `parity` gets the local update g
+ * (three SU(2)-subgroup steps maximising the linearised functional
+ * Re tr(g X), X = sum_k conj(tr M_k) M_k over the eight links M_k at x, each
+ * step over-relaxed with omega), then W_mu(x) <- g W_mu(x),
+ * W_mu(x-mu) <- W_mu(x-mu) g^dagger, G(x) <- g G(x).  W and G must not alias. */
+mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parity,
+                         double omega, void *stream);
+/* Fix U to MCG.  G holds the start transform on entry (mcg_gauge_identity for
+ * plain fixing; the smeared field's transform for the preconditioned re-fix)
+ * and the total transform on exit; U is not modified.  The working field
+ * W = U^G lives in context scratch.  Returns MCG_OK or MCG_WNOTCONV. */
+mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix_opts *opts,
+                   mcg_fix_result *res, void *stream);
+/* Fix B independent fields (Gribov copies and/or lattices of unequal sizes,
+ * one precision) concurrently: each half-sweep is ONE launch over all the
+ * fields, and the sweep loop runs as a captured hipGraph replayed per block
+ * of reunit_every sweeps, with per-field stop flags on the device.  opts is
+ * an array of B entries (tol and max_sweeps may differ; omega, reunit_every
+ * and start_sweep must agree).  Each field's result equals, bit for bit, the
+ * result of mcg_fix on it alone.  U[b] and G[b] as in mcg_fix. */
+mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge *G,
+                         const mcg_fix_opts *opts, mcg_fix_result *res, void *stream);
+
+/* ---- kernel variants and autotuning ------------------------------------------------ */
+/* The half-sweep kernel has MCG_NUM_VARIANTS variants: variant v uses blocks
+ * of {64, 128, 256}[v % 3] threads and targets 1 + v / 3 waves per SIMD.
+ * mcg_autotune times every variant on a scratch copy of U (G = 1; U is not
+ * modified), keeps the fastest for U's precision in the context and returns
+ * it (best_variant, ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host).  The
+ * variant fixes the block decomposition of every fixing kernel, hence the
+ * order of the FP64 partial sums: results at one variant are deterministic. */
+#define MCG_NUM_VARIANTS 6
+mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant,
+                        double *ms_per_halfsweep, void *stream);
+mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant);
+mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
+
+/* ---- centre projection and P-vortices (Sec. II.A) -------------------------------- */
+/* Z = centre integer of every link of U^G (G nullable: U as given), decided
+ * in FP64; *min_margin (nullable, host) = min over links of
+ * pi/3 - |arg(t e^{-2 pi i m/3})|. */
+mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G,
+                              int8_t *Z, double *min_margin, void *stream);
+/* P-vortex plaquettes of Z: n = (m_mu(x) + m_nu(x+mu) - m_mu(x+nu) - m_nu(x)) mod 3
+ * for mu < nu; counts of n != 0 in total, per plane (0,1),(0,2),(0,3),(1,2),
+ * (1,3),(2,3), and per charge n = 1, 2 (host outputs; per_plane/per_charge
+ * nullable). */
+mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t *total,
+                              int64_t *per_plane, int64_t *per_charge, void *stream);
+
+/* ---- gradient of the smeared-field functional ---------------------------------- */
+/* L = R(S_n(U; rho, eps)^{G*}) at fixed G* (at a converged maximum this is
+ * dL/dtheta of the fixed functional by the envelope theorem).  Returns the
+ * ambient gradient gradU = dL/dRe U + i dL/dIm U (same layout and precision
+ * as U) and host scalars L, dL/drho, dL/deps.  Smeared fields are
+ * checkpointed every ckpt_every steps and recomputed between checkpoints. */
+mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps,
+                                  int32_t n, const mcg_gauge *Gstar, int32_t ckpt_every,
+                                  mcg_field *gradU, double *loss, double *dRho, double *dEps,
+                                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

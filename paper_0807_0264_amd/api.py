@@ -1,0 +1,358 @@
+"""Thin Python binding of libmcg.so: argument marshalling only.
+
+Device memory comes from torch tensors on a ROCm device; every computation
+runs in the gfx950 kernels behind the C ABI (include/mcg.h).  Names follow
+the C calls: smear, fix, apply_gauge, center_project, count_vortices, ...
+
+Fields handed to the library are `Links` (internal even/odd
+structure-of-arrays layout, FP64 or FP32) and `GaugeField` (FP64).  Use
+`to_links` / `from_links` and `to_gauge` / `from_gauge` to convert from and
+to the interchange layout complex [Lt, Lz, Ly, Lx, 4, 3, 3] / [Lt, Lz, Ly, Lx, 3, 3].
+"""
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi as A
+
+
+class MCGError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_ctx_cache = {}
+
+
+def context(device=None):
+    """The (per-device, per-process) library context."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    idx = dev.index
+    if idx not in _ctx_cache:
+        lib = A.load()
+        h = C.c_void_p()
+        with torch.cuda.device(idx):
+            st = lib.mcg_create(C.byref(h), idx)
+        if st != A.MCG_OK:
+            raise MCGError(st, f"mcg_create(device={idx}) failed")
+        _ctx_cache[idx] = h
+    return _ctx_cache[idx]
+
+
+def _check(st, ctx, allow_warn=False):
+    if st == A.MCG_OK or (allow_warn and st == A.MCG_WNOTCONV):
+        return st
+    lib = A.load()
+    msg = lib.mcg_last_error(ctx).decode() if ctx else lib.mcg_status_string(st).decode()
+    raise MCGError(st, msg)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dims(L):
+    d = A.Dims()
+    for k in range(4):
+        d.L[k] = int(L[k])
+    return d
+
+
+def volume(L):
+    return int(L[0]) * int(L[1]) * int(L[2]) * int(L[3])
+
+
+@dataclass
+class Links:
+    """Link field in the internal layout: `data` is a flat torch tensor."""
+    L: tuple
+    prec: int  # A.MCG_F64 or A.MCG_F32
+    data: torch.Tensor
+
+    def abi(self):
+        f = A.Field()
+        f.d = _dims(self.L)
+        f.prec = self.prec
+        f.ptr = self.data.data_ptr()
+        return f
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.prec == A.MCG_F64 else torch.float32
+
+    def clone(self):
+        return Links(self.L, self.prec, self.data.clone())
+
+
+@dataclass
+class GaugeField:
+    L: tuple
+    data: torch.Tensor  # float64, V * 18 reals
+
+    def abi(self):
+        g = A.Gauge()
+        g.d = _dims(self.L)
+        g.ptr = self.data.data_ptr()
+        return g
+
+    def clone(self):
+        return GaugeField(self.L, self.data.clone())
+
+
+def _prec_of(dtype):
+    if dtype in (torch.float64, torch.complex128, "f64", A.MCG_F64):
+        return A.MCG_F64
+    if dtype in (torch.float32, torch.complex64, "f32", A.MCG_F32):
+        return A.MCG_F32
+    raise ValueError(f"unsupported precision {dtype}")
+
+
+def empty_links(L, prec, device=None):
+    prec = _prec_of(prec)
+    dt = torch.float64 if prec == A.MCG_F64 else torch.float32
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    return Links(tuple(int(v) for v in L), prec, torch.empty(volume(L) * 36, dtype=dt, device=dev))
+
+
+def empty_gauge(L, device=None):
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    return GaugeField(tuple(int(v) for v in L), torch.empty(volume(L) * 18, dtype=torch.float64, device=dev))
+
+
+def dims_of_interchange(U):
+    return (U.shape[3], U.shape[2], U.shape[1], U.shape[0])
+
+
+def to_links(U, prec=None):
+    """Interchange complex tensor [Lt, Lz, Ly, Lx, 4, 3, 3] on the GPU -> Links."""
+    if not U.is_cuda:
+        raise ValueError("to_links expects a GPU tensor")
+    U = U.contiguous()
+    src_prec = _prec_of(U.dtype)
+    out = empty_links(dims_of_interchange(U), src_prec if prec is None else prec, U.device.index)
+    ctx = context(U.device.index)
+    f = out.abi()
+    _check(A.load().mcg_pack_links(ctx, C.c_void_p(U.data_ptr()), src_prec, C.byref(f), _stream()), ctx)
+    return out
+
+
+def from_links(W, dtype=None):
+    dt = dtype or (torch.complex128 if W.prec == A.MCG_F64 else torch.complex64)
+    out = torch.empty((W.L[3], W.L[2], W.L[1], W.L[0], 4, 3, 3), dtype=dt, device=W.data.device)
+    ctx = context(W.data.device.index)
+    f = W.abi()
+    _check(A.load().mcg_unpack_links(ctx, C.byref(f), C.c_void_p(out.data_ptr()), _prec_of(dt), _stream()), ctx)
+    return out
+
+
+def to_gauge(G):
+    """Interchange complex128 tensor [Lt, Lz, Ly, Lx, 3, 3] on the GPU -> GaugeField."""
+    G = G.contiguous().to(torch.complex128)
+    L = (G.shape[3], G.shape[2], G.shape[1], G.shape[0])
+    out = empty_gauge(L, G.device.index)
+    ctx = context(G.device.index)
+    g = out.abi()
+    _check(A.load().mcg_pack_gauge(ctx, C.c_void_p(G.data_ptr()), C.byref(g), _stream()), ctx)
+    return out
+
+
+def from_gauge(G):
+    out = torch.empty((G.L[3], G.L[2], G.L[1], G.L[0], 3, 3), dtype=torch.complex128, device=G.data.device)
+    ctx = context(G.data.device.index)
+    g = G.abi()
+    _check(A.load().mcg_unpack_gauge(ctx, C.byref(g), C.c_void_p(out.data_ptr()), _stream()), ctx)
+    return out
+
+
+def gauge_identity(L, device=None):
+    G = empty_gauge(L, device)
+    ctx = context(G.data.device.index)
+    g = G.abi()
+    _check(A.load().mcg_gauge_identity(ctx, C.byref(g), _stream()), ctx)
+    return G
+
+
+def gauge_reunit(G):
+    ctx = context(G.data.device.index)
+    g = G.abi()
+    _check(A.load().mcg_gauge_reunit(ctx, C.byref(g), _stream()), ctx)
+    return G
+
+
+# ---- the method's calls -----------------------------------------------------------------
+def smear(U, rho, eps=1.0, n=1, out=None):
+    """n stout (eps = 1) or over-improved stout steps (Sec. II.B)."""
+    out = out if out is not None else empty_links(U.L, U.prec, U.data.device.index)
+    ctx = context(U.data.device.index)
+    fu, fo = U.abi(), out.abi()
+    _check(A.load().mcg_smear(ctx, C.byref(fu), C.byref(fo), float(rho), float(eps), int(n), _stream()), ctx)
+    return out
+
+
+def apply_gauge(U, G, out=None):
+    out = out if out is not None else empty_links(U.L, U.prec, U.data.device.index)
+    ctx = context(U.data.device.index)
+    fu, g, fo = U.abi(), G.abi(), out.abi()
+    _check(A.load().mcg_apply_gauge(ctx, C.byref(fu), C.byref(g), C.byref(fo), _stream()), ctx)
+    return out
+
+
+def _scalar(fn, U):
+    ctx = context(U.data.device.index)
+    f = U.abi()
+    v = C.c_double()
+    _check(fn(ctx, C.byref(f), C.byref(v), _stream()), ctx)
+    return v.value
+
+
+def functional(U):
+    """R = (1/N_l) sum |tr U / 3|^2 of the field as given (Sec. II.A)."""
+    return _scalar(A.load().mcg_functional, U)
+
+
+def plaquette(U):
+    return _scalar(A.load().mcg_plaquette, U)
+
+
+def theta(W):
+    return _scalar(A.load().mcg_theta, W)
+
+
+def halfsweep(W, G, parity, omega=1.7):
+    ctx = context(W.data.device.index)
+    f, g = W.abi(), G.abi()
+    _check(A.load().mcg_halfsweep(ctx, C.byref(f), C.byref(g), int(parity), float(omega), _stream()), ctx)
+
+
+def _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj):
+    o = A.FixOpts()
+    o.tol = float(tol)
+    o.omega = float(omega)
+    o.max_sweeps = int(max_sweeps)
+    o.reunit_every = int(reunit_every)
+    o.start_sweep = int(start_sweep)
+    o.check_every = int(check_every)
+    o.traj = traj.ctypes.data_as(C.POINTER(C.c_double)) if traj is not None else None
+    return o
+
+
+def _result(r, traj):
+    out = dict(R=r.R, dR=r.dR, theta=r.theta, sweeps=r.sweeps, blocks50=r.blocks50, status=r.status)
+    if traj is not None:
+        out["traj"] = traj[: r.sweeps + 1].copy()
+    return out
+
+
+def fix(U, G=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50, start_sweep=0,
+        check_every=50, want_traj=False):
+    """MCG-fix U starting from G (identity if None); G is updated in place to the
+    total transform.  Returns (G, info)."""
+    import numpy as np
+    G = G if G is not None else gauge_identity(U.L, U.data.device.index)
+    traj = np.zeros(int(max_sweeps) + 1) if want_traj else None
+    o = _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj)
+    r = A.FixResult()
+    ctx = context(U.data.device.index)
+    fu, g = U.abi(), G.abi()
+    _check(A.load().mcg_fix(ctx, C.byref(fu), C.byref(g), C.byref(o), C.byref(r), _stream()), ctx,
+           allow_warn=True)
+    return G, _result(r, traj)
+
+
+def fix_batch(Us, Gs=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50, start_sweep=0,
+              check_every=50, want_traj=False):
+    """Fix several fields (copies and/or lattices of unequal sizes, one precision)
+    in one batched, graph-captured sweep loop.  tol and max_sweeps may be lists."""
+    import numpy as np
+    B = len(Us)
+    Gs = Gs if Gs is not None else [gauge_identity(U.L, U.data.device.index) for U in Us]
+    tols = tol if isinstance(tol, (list, tuple)) else [tol] * B
+    maxs = max_sweeps if isinstance(max_sweeps, (list, tuple)) else [max_sweeps] * B
+    trajs = [np.zeros(int(m) + 1) if want_traj else None for m in maxs]
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    GG = (A.Gauge * B)(*[G.abi() for G in Gs])
+    O = (A.FixOpts * B)(*[_opts(tols[b], maxs[b], omega, reunit_every, start_sweep, check_every, trajs[b])
+                          for b in range(B)])
+    R = (A.FixResult * B)()
+    ctx = context(Us[0].data.device.index)
+    _check(A.load().mcg_fix_batch(ctx, B, F, GG, O, R, _stream()), ctx, allow_warn=True)
+    return Gs, [_result(R[b], trajs[b]) for b in range(B)]
+
+
+def center_project(U, G=None):
+    """Centre integers Z (int8 tensor [4, V], lexicographic sites) of U^G and the
+    minimum centre-phase margin (Sec. II.A)."""
+    Z = torch.empty((4, volume(U.L)), dtype=torch.int8, device=U.data.device)
+    ctx = context(U.data.device.index)
+    f = U.abi()
+    g = G.abi() if G is not None else None
+    mm = C.c_double()
+    _check(A.load().mcg_center_project(ctx, C.byref(f), C.byref(g) if g is not None else None,
+                                       C.c_void_p(Z.data_ptr()), C.byref(mm), _stream()), ctx)
+    return Z, mm.value
+
+
+def count_vortices(Z, L):
+    ctx = context(Z.device.index)
+    tot = C.c_int64()
+    pp = (C.c_int64 * 6)()
+    pc = (C.c_int64 * 2)()
+    _check(A.load().mcg_count_vortices(ctx, C.c_void_p(Z.data_ptr()), _dims(L), C.byref(tot), pp, pc,
+                                       _stream()), ctx)
+    return dict(total=tot.value, per_plane=list(pp), per_charge=list(pc))
+
+
+def smear_mcg_backward(U, rho, eps, n, Gstar, ckpt_every=5):
+    """Gradient of L = R(S_n(U; rho, eps)^{G*}) at fixed G*: returns
+    (gradU Links (ambient), L, dL/drho, dL/deps)."""
+    grad = empty_links(U.L, U.prec, U.data.device.index)
+    ctx = context(U.data.device.index)
+    fu, g, fg = U.abi(), Gstar.abi(), grad.abi()
+    loss, dr, de = C.c_double(), C.c_double(), C.c_double()
+    _check(A.load().mcg_smear_mcg_backward(ctx, C.byref(fu), float(rho), float(eps), int(n), C.byref(g),
+                                           int(ckpt_every), C.byref(fg), C.byref(loss), C.byref(dr),
+                                           C.byref(de), _stream()), ctx)
+    return grad, loss.value, dr.value, de.value
+
+
+def autotune(U):
+    """Time every half-sweep variant on a copy of U; keep and return the fastest."""
+    ctx = context(U.data.device.index)
+    f = U.abi()
+    best = C.c_int32()
+    ms = (C.c_double * A.MCG_NUM_VARIANTS)()
+    _check(A.load().mcg_autotune(ctx, C.byref(f), C.byref(best), ms, _stream()), ctx)
+    return best.value, list(ms)
+
+
+def set_variant(prec, variant, device=None):
+    ctx = context(device)
+    _check(A.load().mcg_set_variant(ctx, _prec_of(prec), int(variant)), ctx)
+
+
+def get_variant(prec, device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_variant(ctx, _prec_of(prec), C.byref(v)), ctx)
+    return v.value
+
+
+# ---- the paper's pipeline (Sec. II.B) ----------------------------------------------------
+def precondition_and_fix(U, rho=0.1, eps=1.0, n=10, tol=1e-7, max_sweeps=5000, omega=1.7,
+                         reunit_every=50, check_every=50):
+    """Smear U, fix the smeared field, carry its transform back to U and fix
+    again, then centre-project and count P-vortices."""
+    S = smear(U, rho, eps, n)
+    Gs, info_s = fix(S, None, tol, max_sweeps, omega, reunit_every, 0, check_every)
+    R_smeared = info_s["R"]
+    del S
+    G, info = fix(U, Gs, tol, max_sweeps, omega, reunit_every, 0, check_every)
+    Z, margin = center_project(U, G)
+    vort = count_vortices(Z, U.L)
+    nplaq = 6 * volume(U.L)
+    return dict(G=G, Z=Z, R_smeared=R_smeared, R=info["R"], sweeps_smeared=info_s["sweeps"],
+                sweeps=info["sweeps"], blocks50=(info_s["sweeps"] + info["sweeps"] + 49) // 50,
+                min_margin=margin, vortices=vort, vortex_fraction=vort["total"] / nplaq,
+                info_smeared=info_s, info=info)

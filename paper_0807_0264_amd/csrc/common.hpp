@@ -1,0 +1,334 @@
+// common.hpp -- device-side building blocks of the gfx950 MCG library:
+// complex and 3x3 complex matrix arithmetic, lattice geometry of the
+// even/odd structure-of-arrays layout, link I/O and deterministic block
+// reductions.  Everything is templated on the link precision T (float or
+// double); gauge transforms are always double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcg {
+
+template <typename T> struct V2t;
+template <> struct V2t<float> { using type = float2; };
+template <> struct V2t<double> { using type = double2; };
+template <typename T> using V2 = typename V2t<T>::type;
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cx {
+  T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> cmk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return cx<T>{a.re + b.re, a.im + b.im};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return cx<T>{a.re - b.re, a.im - b.im};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return cx<T>{s * a.re, s * a.im};
+}
+template <typename T> __device__ __forceinline__ cx<T> conj(cx<T> a) { return cx<T>{a.re, -a.im}; }
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cx<T> mulc(cx<T> a, cx<T> b) {
+  return cx<T>{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return cx<T>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename To, typename From> __device__ __forceinline__ cx<To> cvt(cx<From> a) {
+  return cx<To>{(To)a.re, (To)a.im};
+}
+
+// ------------------------------------------------------------ 3x3 matrices
+template <typename T> struct M3 {
+  cx<T> e[9];
+};
+
+template <typename T> __device__ __forceinline__ M3<T> m_zero() {
+  M3<T> r;
+#pragma unroll
+  for (int k = 0; k < 9; k++) r.e[k] = cx<T>{T(0), T(0)};
+  return r;
+}
+template <typename T> __device__ __forceinline__ M3<T> m_ident() {
+  M3<T> r = m_zero<T>();
+  r.e[0].re = r.e[4].re = r.e[8].re = T(1);
+  return r;
+}
+template <typename To, typename From> __device__ __forceinline__ M3<To> m_cvt(const M3<From> &a) {
+  M3<To> r;
+#pragma unroll
+  for (int k = 0; k < 9; k++) r.e[k] = cvt<To>(a.e[k]);
+  return r;
+}
+// a b
+template <typename T> __device__ __forceinline__ M3<T> mul(const M3<T> &a, const M3<T> &b) {
+  M3<T> c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      c.e[3 * i + j] = a.e[3 * i] * b.e[j] + a.e[3 * i + 1] * b.e[3 + j] + a.e[3 * i + 2] * b.e[6 + j];
+  return c;
+}
+// a b^dagger
+template <typename T> __device__ __forceinline__ M3<T> mul_nd(const M3<T> &a, const M3<T> &b) {
+  M3<T> c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      c.e[3 * i + j] = mulc(a.e[3 * i], b.e[3 * j]) + mulc(a.e[3 * i + 1], b.e[3 * j + 1]) +
+                       mulc(a.e[3 * i + 2], b.e[3 * j + 2]);
+  return c;
+}
+// a^dagger b
+template <typename T> __device__ __forceinline__ M3<T> mul_dn(const M3<T> &a, const M3<T> &b) {
+  M3<T> c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+      c.e[3 * i + j] = cmul(a.e[i], b.e[j]) + cmul(a.e[3 + i], b.e[3 + j]) + cmul(a.e[6 + i], b.e[6 + j]);
+  return c;
+}
+template <typename T> __device__ __forceinline__ M3<T> dag(const M3<T> &a) {
+  M3<T> c;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) c.e[3 * i + j] = conj(a.e[3 * j + i]);
+  return c;
+}
+template <typename T> __device__ __forceinline__ cx<T> trace(const M3<T> &a) {
+  return a.e[0] + a.e[4] + a.e[8];
+}
+// c += s a (complex s)
+template <typename T> __device__ __forceinline__ void axpy(cx<T> s, const M3<T> &a, M3<T> &c) {
+#pragma unroll
+  for (int k = 0; k < 9; k++) c.e[k] = c.e[k] + s * a.e[k];
+}
+template <typename T> __device__ __forceinline__ void add_to(const M3<T> &a, M3<T> &c) {
+#pragma unroll
+  for (int k = 0; k < 9; k++) c.e[k] = c.e[k] + a.e[k];
+}
+template <typename T> __device__ __forceinline__ M3<T> scale(T s, const M3<T> &a) {
+  M3<T> c;
+#pragma unroll
+  for (int k = 0; k < 9; k++) c.e[k] = s * a.e[k];
+  return c;
+}
+// traceless anti-Hermitian part: (1/2)(M - M^dag) - (1/6) tr(M - M^dag) 1
+template <typename T> __device__ __forceinline__ M3<T> ta(const M3<T> &m) {
+  M3<T> o;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      cx<T> a = m.e[3 * i + j], b = m.e[3 * j + i];
+      o.e[3 * i + j] = cx<T>{T(0.5) * (a.re - b.re), T(0.5) * (a.im + b.im)};
+    }
+  // tr(M - M^dag) = 2i Im tr M
+  T im3 = (m.e[0].im + m.e[4].im + m.e[8].im) * T(1.0 / 3.0);
+  o.e[0].im -= im3;
+  o.e[4].im -= im3;
+  o.e[8].im -= im3;
+  return o;
+}
+// Re tr(a^dagger b)
+template <typename T> __device__ __forceinline__ T rdot(const M3<T> &a, const M3<T> &b) {
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < 9; k++) s += a.e[k].re * b.e[k].re + a.e[k].im * b.e[k].im;
+  return s;
+}
+// |tr M|^2 evaluated in double from the stored precision
+template <typename T> __device__ __forceinline__ double tr2(const M3<T> &a) {
+  cx<T> t = trace(a);
+  double r = (double)t.re, i = (double)t.im;
+  return r * r + i * i;
+}
+
+// Gram-Schmidt on the rows; third row = conj(r0 x r1), so det = +1.
+__device__ __forceinline__ void reunit(M3<double> &m) {
+  double n0 = norm2(m.e[0]) + norm2(m.e[1]) + norm2(m.e[2]);
+  double i0 = 1.0 / sqrt(n0);
+#pragma unroll
+  for (int k = 0; k < 3; k++) m.e[k] = i0 * m.e[k];
+  cx<double> ip = cmul(m.e[0], m.e[3]) + cmul(m.e[1], m.e[4]) + cmul(m.e[2], m.e[5]);
+#pragma unroll
+  for (int k = 0; k < 3; k++) m.e[3 + k] = m.e[3 + k] - ip * m.e[k];
+  double n1 = norm2(m.e[3]) + norm2(m.e[4]) + norm2(m.e[5]);
+  double i1 = 1.0 / sqrt(n1);
+#pragma unroll
+  for (int k = 3; k < 6; k++) m.e[k] = i1 * m.e[k];
+  m.e[6] = conj(m.e[1] * m.e[5] - m.e[2] * m.e[4]);
+  m.e[7] = conj(m.e[2] * m.e[3] - m.e[0] * m.e[5]);
+  m.e[8] = conj(m.e[0] * m.e[4] - m.e[1] * m.e[3]);
+}
+
+// ---------------------------------------------------------------- geometry
+// Sites are split by parity; within a parity, the half index is h = i >> 1
+// with i = x + Lx*(y + Ly*(z + Lz*t)) (Lx is even, so i and i^1 have opposite
+// parity and the same h).
+struct Geom {
+  int L[4];
+  int V, Vh, hx;  // sites, sites per parity, Lx / 2
+};
+
+__device__ __forceinline__ void coords_of(const Geom &g, int par, int h, int c[4]) {
+  int r = h / g.hx;
+  int xh = h - r * g.hx;
+  int r2 = r / g.L[1];
+  int y = r - r2 * g.L[1];
+  int t = r2 / g.L[2];
+  int z = r2 - t * g.L[2];
+  c[0] = 2 * xh + ((par + y + z + t) & 1);
+  c[1] = y;
+  c[2] = z;
+  c[3] = t;
+}
+__device__ __forceinline__ int lex_index(const Geom &g, const int c[4]) {
+  return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+__device__ __forceinline__ int half_index(const Geom &g, const int c[4]) {
+  return lex_index(g, c) >> 1;
+}
+__device__ __forceinline__ int parity_of(const int c[4]) { return (c[0] + c[1] + c[2] + c[3]) & 1; }
+// coordinates moved by `step` (|step| < L) along mu, periodic
+__device__ __forceinline__ void moved(const Geom &g, const int c[4], int mu, int step, int d[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) d[k] = c[k];
+  int v = c[mu] + step;
+  int Lm = g.L[mu];
+  v = v >= Lm ? v - Lm : v;
+  v = v < 0 ? v + Lm : v;
+  d[mu] = v;
+}
+
+// ------------------------------------------------------------------ I/O
+// Loads and stores address a plane through a wave-uniform base pointer plus a
+// 32-bit per-lane byte offset, so the compiler can use the scalar-base form
+// of global memory instructions and keeps no 64-bit per-lane addresses live.
+template <typename V>
+__device__ __forceinline__ V ld_plane(const V *plane, unsigned byte_off) {
+  return *(const V *)((const char *)plane + byte_off);
+}
+template <typename V>
+__device__ __forceinline__ void st_plane(V *plane, unsigned byte_off, V v) {
+  *(V *)((char *)plane + byte_off) = v;
+}
+
+// complex element (mu, par, k, h) at ((mu*2 + par)*9 + k)*Vh + h
+//   = (mu*18 + k)*Vh  [uniform]  +  par*9*Vh + h  [per lane]
+template <typename T> struct Links {
+  V2<T> *p;
+  int Vh;
+  __device__ __forceinline__ unsigned off(int par, int h) const {
+    return (unsigned)(par * 9 * Vh + h) * (unsigned)sizeof(V2<T>);
+  }
+  __device__ __forceinline__ M3<T> load_off(int mu, unsigned o) const {
+    M3<T> m;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      const V2<T> v = ld_plane(p + (size_t)(mu * 18 + k) * Vh, o);
+      m.e[k] = cx<T>{v.x, v.y};
+    }
+    return m;
+  }
+  __device__ __forceinline__ void store_off(int mu, unsigned o, const M3<T> &m) const {
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      V2<T> v;
+      v.x = m.e[k].re;
+      v.y = m.e[k].im;
+      st_plane(p + (size_t)(mu * 18 + k) * Vh, o, v);
+    }
+  }
+  __device__ __forceinline__ M3<T> load(int mu, int par, int h) const { return load_off(mu, off(par, h)); }
+  __device__ __forceinline__ void store(int mu, int par, int h, const M3<T> &m) const {
+    store_off(mu, off(par, h), m);
+  }
+  // link mu at the site with coordinates c
+  __device__ __forceinline__ M3<T> at(const Geom &g, const int c[4], int mu) const {
+    return load(mu, parity_of(c), half_index(g, c));
+  }
+};
+
+// complex element (par, k, h) at (par*9 + k)*Vh + h
+struct Gauge {
+  double2 *p;
+  int Vh;
+  __device__ __forceinline__ unsigned off(int par, int h) const {
+    return (unsigned)(par * 9 * Vh + h) * (unsigned)sizeof(double2);
+  }
+  __device__ __forceinline__ M3<double> load(int par, int h) const {
+    const unsigned o = off(par, h);
+    M3<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      const double2 v = ld_plane(p + (size_t)k * Vh, o);
+      m.e[k] = cx<double>{v.x, v.y};
+    }
+    return m;
+  }
+  __device__ __forceinline__ void store(int par, int h, const M3<double> &m) const {
+    const unsigned o = off(par, h);
+#pragma unroll
+    for (int k = 0; k < 9; k++) st_plane(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
+  }
+};
+
+// ------------------------------------------------------------- reductions
+// Deterministic block sum of one double per thread: butterfly within each
+// 64-wide wavefront, then the per-wave sums in wave order.  Result valid in
+// thread 0.  BS must be a multiple of 64.
+template <int BS> __device__ __forceinline__ double block_sum(double v) {
+  __shared__ double part[BS / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < BS / 64; i++) r += part[i];
+  }
+  __syncthreads();  // part[] may be reused by a later call
+  return r;
+}
+template <int BS> __device__ __forceinline__ double block_min(double v) {
+  __shared__ double part[BS / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  double r = v;
+  if (threadIdx.x == 0) {
+    r = part[0];
+#pragma unroll
+    for (int i = 1; i < BS / 64; i++) r = fmin(r, part[i]);
+  }
+  __syncthreads();
+  return r;
+}
+// Fixed-order sum of n partials by one block: thread t adds t, t+BS, ...
+// in order, then block_sum.  Result valid in thread 0.
+template <int BS> __device__ __forceinline__ double sum_partials(const double *p, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+  return block_sum<BS>(s);
+}
+
+}  // namespace mcg

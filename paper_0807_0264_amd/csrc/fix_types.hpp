@@ -1,0 +1,41 @@
+// fix_types.hpp -- structures shared by the host driver and the fixing
+// kernels: the per-field device state of the sweep loop and the descriptor
+// of one field inside a (possibly batched) launch.
+#pragma once
+
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mcg {
+
+// Device-resident state of one field's fixing loop.  Written only by the
+// single-block bookkeeping kernels (init / reset / check / final).
+struct FixState {
+  double R_prev;   // R before the current sweep
+  double R_last;   // R after the last sweep
+  double dR;       // R_last - R_prev of the last sweep
+  double R_final;  // R after the final re-unitarisation
+  double theta;    // stationarity residual of the final field
+  double tol;
+  int32_t k;       // sweeps done in this call
+  int32_t max_k;   // sweeps allowed in this call
+  int32_t done;    // 1 once converged or out of sweeps: every gated kernel exits at once
+  int32_t status;  // 0 converged, 1 not converged
+  int32_t pad0, pad1;
+};
+
+// One field in a launch.  Blocks [blk0, blk0 + nblk) of a batched grid work
+// on this field; block j covers half indices [j*BS, (j+1)*BS).
+template <typename T> struct LatDesc {
+  Geom g;
+  int blk0, nblk;
+  V2<T> *W;        // working field U^G (updated in place)
+  const V2<T> *U;  // the field being fixed (read only)
+  double2 *G;      // gauge transform (FP64)
+  FixState *st;
+  double *part;    // nblk partial sums
+  double *traj;    // device copy of the R trajectory (max_k + 1) or null
+};
+
+}  // namespace mcg

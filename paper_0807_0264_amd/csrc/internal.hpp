@@ -1,0 +1,69 @@
+// internal.hpp -- host-side declarations of the kernel launchers (one per
+// .hip translation unit).  All launchers enqueue on the given stream and
+// return the launch status; `D` points to a device table of LatDesc<T>.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mcg {
+
+// k_mcg.hip -- fixing (bs = block size of the half-index grid; the
+// half-sweep takes a variant = block size and occupancy, see variant_block)
+constexpr int NUM_VARIANTS = 6;
+inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 256); }
+template <typename T>
+hipError_t launch_halfsweep(int variant, const void *D, int B, int blocks, int par, double omega,
+                            bool withR, bool gated, hipStream_t s);
+template <typename T>
+hipError_t launch_rederive(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s);
+template <typename T>
+hipError_t launch_reunit(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s);
+template <typename T>
+hipError_t launch_theta(int bs, const void *D, int B, int blocks, hipStream_t s);
+template <typename T> hipError_t launch_book(const void *D, int B, int what, hipStream_t s);
+enum { BOOK_INIT = 0, BOOK_RESET = 1, BOOK_CHECK = 2, BOOK_FINAL = 3, BOOK_THETA = 4 };
+
+// k_field.hip -- layout conversion and whole-field measurements
+template <typename Tin, typename Tout>
+hipError_t launch_pack_links(const Geom &g, const void *src, void *dst, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_unpack_links(const Geom &g, const void *src, void *dst, hipStream_t s);
+hipError_t launch_pack_gauge(const Geom &g, const double *src, double *dst, hipStream_t s);
+hipError_t launch_unpack_gauge(const Geom &g, const double *src, double *dst, hipStream_t s);
+hipError_t launch_gauge_identity(const Geom &g, double *G, hipStream_t s);
+hipError_t launch_gauge_reunit(const Geom &g, double *G, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_gauge(const Geom &g, const void *U, const double *G, void *out, hipStream_t s);
+// per-block partial sums into `part` (ceil(Vh/256) entries), then final sum into *out
+template <typename T>
+hipError_t launch_functional(const Geom &g, const void *U, double *part, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_plaquette(const Geom &g, const void *U, double *part, double *out, hipStream_t s);
+int field_blocks256(const Geom &g);
+
+// k_smear.hip -- one stout / over-improved stout step; sets *flag if an
+// exponent needed scaling beyond the series' range
+template <typename T>
+hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
+                             hipStream_t s);
+
+// k_project.hip -- centre projection and vortex counting
+template <typename T>
+hipError_t launch_center_project(const Geom &g, const void *U, const double *G, int8_t *Z,
+                                 double *part, double *min_out, hipStream_t s);
+hipError_t launch_count_vortices(const Geom &g, const int8_t *Z, unsigned long long *counts,
+                                 hipStream_t s);
+
+// k_backward.hip -- adjoint of one smearing step and the loss seed
+template <typename T>
+hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
+                            double *loss_out, hipStream_t s);
+template <typename T>
+hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU,
+                               void *gC, double rho, double eps, double *part2,
+                               double *sums_out, hipStream_t s);
+
+}  // namespace mcg

@@ -1,0 +1,772 @@
+// mcg_api.cpp -- the C ABI declared in include/mcg.h: context and scratch
+// management, argument checks, precision dispatch, the sweep driver of the
+// fixing iteration (direct launches for a single field, a captured hipGraph
+// per block of sweeps for batches) and the block-size autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "fix_types.hpp"
+#include "internal.hpp"
+#include "mcg.h"
+
+using namespace mcg;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct mcg_ctx {
+  int device = 0;
+  std::string err;
+  hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
+  DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part;
+  std::vector<DevBuf> W, fpart, traj;
+  void *h_pinned = nullptr;
+  size_t h_pinned_cap = 0;
+  int variant[2] = {2, 2};  // half-sweep variant per precision (MCG_F64, MCG_F32)
+};
+
+namespace {
+
+mcg_status fail(mcg_ctx *ctx, mcg_status s, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, MCG_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                    \
+  } while (0)
+
+mcg_status ensure(mcg_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return MCG_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    if (e != hipSuccess) return fail(ctx, MCG_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, MCG_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  b.cap = bytes;
+  return MCG_OK;
+}
+
+mcg_status ensure_pinned(mcg_ctx *ctx, size_t bytes) {
+  if (ctx->h_pinned_cap >= bytes) return MCG_OK;
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  ctx->h_pinned = nullptr;
+  ctx->h_pinned_cap = 0;
+  if (hipHostMalloc(&ctx->h_pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MCG_ENOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  ctx->h_pinned_cap = bytes;
+  return MCG_OK;
+}
+
+bool dims_valid(const mcg_dims &d) {
+  int64_t V = 1;
+  for (int k = 0; k < 4; k++) {
+    if (d.L[k] < 2 || (d.L[k] & 1)) return false;
+    V *= d.L[k];
+  }
+  // 32-bit site indices; 72 complex planes of V/2 must fit in 31 bits
+  return V <= (int64_t(1) << 30) && 72 * (V / 2) < (int64_t(1) << 31);
+}
+
+Geom geom_of(const mcg_dims &d) {
+  Geom g;
+  for (int k = 0; k < 4; k++) g.L[k] = d.L[k];
+  g.V = d.L[0] * d.L[1] * d.L[2] * d.L[3];
+  g.Vh = g.V / 2;
+  g.hx = d.L[0] / 2;
+  return g;
+}
+
+bool same_dims(const mcg_dims &a, const mcg_dims &b) {
+  return a.L[0] == b.L[0] && a.L[1] == b.L[1] && a.L[2] == b.L[2] && a.L[3] == b.L[3];
+}
+
+mcg_status check_field(mcg_ctx *ctx, const mcg_field *f, const char *name) {
+  if (!f) return fail(ctx, MCG_EINVAL, "%s is NULL", name);
+  if (!dims_valid(f->d))
+    return fail(ctx, MCG_EINVAL, "%s: extents (%d,%d,%d,%d) must be even, >= 2, V <= 2^30", name,
+                f->d.L[0], f->d.L[1], f->d.L[2], f->d.L[3]);
+  if (f->prec != MCG_F64 && f->prec != MCG_F32) return fail(ctx, MCG_EINVAL, "%s: bad precision %d", name, f->prec);
+  if (!f->ptr) return fail(ctx, MCG_EINVAL, "%s: NULL data pointer", name);
+  return MCG_OK;
+}
+
+mcg_status check_gauge(mcg_ctx *ctx, const mcg_gauge *G, const mcg_dims &d, const char *name) {
+  if (!G || !G->ptr) return fail(ctx, MCG_EINVAL, "%s is NULL", name);
+  if (!same_dims(G->d, d)) return fail(ctx, MCG_EINVAL, "%s: extents differ from the field's", name);
+  return MCG_OK;
+}
+
+size_t field_bytes(const mcg_dims &d, int prec) {
+  if (!dims_valid(d)) return 0;
+  size_t V = (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3];
+  return V * 36 * (prec == MCG_F64 ? sizeof(double) : sizeof(float));
+}
+
+int nblocks(const Geom &g, int bs) { return (g.Vh + bs - 1) / bs; }
+
+// ------------------------------------------------------------ fixing driver
+template <typename T> struct FixRun {
+  mcg_ctx *ctx;
+  hipStream_t s;
+  int B, variant, bs, total_blocks;
+  void *dD;  // device LatDesc table
+  double omega;
+
+  mcg_status sweep(bool reunit_first) {
+    if (reunit_first) {
+      HIPCHK(launch_reunit<T>(bs, dD, B, total_blocks, true, s));
+      HIPCHK(launch_rederive<T>(bs, dD, B, total_blocks, true, s));
+      HIPCHK(launch_book<T>(dD, B, BOOK_RESET, s));
+    }
+    HIPCHK(launch_halfsweep<T>(variant, dD, B, total_blocks, 0, omega, false, true, s));
+    HIPCHK(launch_halfsweep<T>(variant, dD, B, total_blocks, 1, omega, true, true, s));
+    HIPCHK(launch_book<T>(dD, B, BOOK_CHECK, s));
+    return MCG_OK;
+  }
+};
+
+template <typename T>
+mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const mcg_fix_opts *opts,
+                    mcg_fix_result *res, hipStream_t s, bool batch) {
+  const int prec = std::is_same<T, double>::value ? MCG_F64 : MCG_F32;
+  if (B < 1) return fail(ctx, MCG_EINVAL, "batch size %d < 1", B);
+  if (!U || !G || !opts || !res) return fail(ctx, MCG_EINVAL, "NULL argument");
+  const double omega = opts[0].omega;
+  const int re = opts[0].reunit_every, s0 = opts[0].start_sweep;
+  const int check_every = std::max(1, opts[0].check_every);
+  int kmax = 0;
+  for (int b = 0; b < B; b++) {
+    mcg_status st = check_field(ctx, &U[b], "U");
+    if (st) return st;
+    if (U[b].prec != prec) return fail(ctx, MCG_EINVAL, "field %d: precision differs within the batch", b);
+    if ((st = check_gauge(ctx, &G[b], U[b].d, "G"))) return st;
+    const mcg_fix_opts &o = opts[b];
+    if (o.max_sweeps < 0) return fail(ctx, MCG_EINVAL, "max_sweeps < 0");
+    if (o.reunit_every < 1) return fail(ctx, MCG_EINVAL, "reunit_every < 1");
+    if (!(o.omega >= 0.0 && o.omega <= 2.0)) return fail(ctx, MCG_EINVAL, "omega must lie in [0, 2]");
+    if (std::isnan(o.tol)) return fail(ctx, MCG_EINVAL, "tol is NaN");
+    if (o.omega != omega || o.reunit_every != re || o.start_sweep != s0)
+      return fail(ctx, MCG_EINVAL, "omega, reunit_every and start_sweep must agree across the batch");
+    kmax = std::max(kmax, o.max_sweeps);
+    for (int c = 0; c < b; c++)
+      if (U[c].ptr == U[b].ptr && G[c].ptr == G[b].ptr)
+        return fail(ctx, MCG_EINVAL, "fields %d and %d share U and G", c, b);
+  }
+  const int variant = ctx->variant[prec], bs = variant_block(variant);
+  if ((int)ctx->W.size() < B) {
+    ctx->W.resize(B);
+    ctx->fpart.resize(B);
+    ctx->traj.resize(B);
+  }
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->states, sizeof(FixState) * B))) return st;
+  if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>) * B))) return st;
+  if ((st = ensure_pinned(ctx, (sizeof(LatDesc<T>) + sizeof(FixState)) * B + 64))) return st;
+  LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
+  FixState *hS = (FixState *)(hD + B);
+  int total = 0;
+  for (int b = 0; b < B; b++) {
+    const Geom g = geom_of(U[b].d);
+    const int nb = nblocks(g, bs);
+    if ((st = ensure(ctx, ctx->W[b], field_bytes(U[b].d, prec)))) return st;
+    if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb))) return st;
+    const bool want_traj = opts[b].traj != nullptr;
+    if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
+    LatDesc<T> d;
+    d.g = g;
+    d.blk0 = total;
+    d.nblk = nb;
+    d.W = (V2<T> *)ctx->W[b].p;
+    d.U = (const V2<T> *)U[b].ptr;
+    d.G = (double2 *)G[b].ptr;
+    d.st = (FixState *)ctx->states.p + b;
+    d.part = (double *)ctx->fpart[b].p;
+    d.traj = want_traj ? (double *)ctx->traj[b].p : nullptr;
+    hD[b] = d;
+    FixState f;
+    memset(&f, 0, sizeof f);
+    f.tol = opts[b].tol;
+    f.max_k = opts[b].max_sweeps;
+    hS[b] = f;
+    total += nb;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
+  // the pinned staging area is reused below: wait for these copies first
+  HIPCHK(hipStreamSynchronize(s));
+
+  FixRun<T> run{ctx, s, B, variant, bs, total, ctx->desc.p, omega};
+  HIPCHK(launch_rederive<T>(bs, run.dD, B, total, false, s));
+  HIPCHK(launch_book<T>(run.dD, B, BOOK_INIT, s));
+
+  auto all_done = [&](bool &done) -> mcg_status {
+    HIPCHK(hipMemcpyAsync(hS, ctx->states.p, sizeof(FixState) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    done = true;
+    for (int b = 0; b < B; b++) done = done && hS[b].done;
+    return MCG_OK;
+  };
+  auto due = [&](int k) { return k > 1 && (s0 + k - 1) % re == 0; };
+
+  int issued = 0;
+  bool done = kmax == 0;
+  if (!batch) {
+    while (!done && issued < kmax) {
+      const int chunk = std::min(check_every, kmax - issued);
+      for (int j = 0; j < chunk; j++) {
+        ++issued;
+        if ((st = run.sweep(due(issued)))) return st;
+      }
+      if ((st = all_done(done))) return st;
+    }
+  } else {
+    // sweeps up to the next re-unitarisation boundary go directly ...
+    while (!done && issued < kmax && !(issued > 0 && due(issued + 1))) {
+      ++issued;
+      if ((st = run.sweep(due(issued)))) return st;
+      if (issued % check_every == 0 && (st = all_done(done))) return st;
+    }
+    if (!done && (st = all_done(done))) return st;
+    // ... then whole blocks [re-unitarise, re sweeps] replay one captured graph
+    if (!done && issued < kmax && kmax - issued >= re) {
+      if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      FixRun<T> cap = run;
+      cap.s = ctx->cap_stream;
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+      mcg_status cst = MCG_OK;
+      for (int j = 0; j < re && cst == MCG_OK; j++) cst = cap.sweep(j == 0);
+      hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+      if (cst) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return cst;
+      }
+      if (e != hipSuccess) return fail(ctx, MCG_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, MCG_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+      }
+      while (!done && kmax - issued >= re) {
+        e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) break;
+        issued += re;
+        mcg_status q = all_done(done);
+        if (q) {
+          (void)hipGraphExecDestroy(exec);
+          (void)hipGraphDestroy(graph);
+          return q;
+        }
+      }
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(ctx, MCG_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+    }
+    while (!done && issued < kmax) {
+      ++issued;
+      if ((st = run.sweep(due(issued)))) return st;
+      if (issued % check_every == 0 && (st = all_done(done))) return st;
+    }
+  }
+  // final re-unitarisation, R and the stationarity residual
+  HIPCHK(launch_reunit<T>(bs, run.dD, B, total, false, s));
+  HIPCHK(launch_rederive<T>(bs, run.dD, B, total, false, s));
+  HIPCHK(launch_book<T>(run.dD, B, BOOK_FINAL, s));
+  HIPCHK(launch_theta<T>(bs, run.dD, B, total, s));
+  HIPCHK(launch_book<T>(run.dD, B, BOOK_THETA, s));
+  HIPCHK(hipMemcpyAsync(hS, ctx->states.p, sizeof(FixState) * B, hipMemcpyDeviceToHost, s));
+  for (int b = 0; b < B; b++)
+    if (opts[b].traj && ctx->traj[b].p)
+      HIPCHK(hipMemcpyAsync(opts[b].traj, ctx->traj[b].p, sizeof(double) * (opts[b].max_sweeps + 1),
+                            hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  mcg_status worst = MCG_OK;
+  for (int b = 0; b < B; b++) {
+    mcg_fix_result &r = res[b];
+    r.R = hS[b].R_final;
+    r.dR = hS[b].dR;
+    r.theta = hS[b].theta;
+    r.sweeps = hS[b].k;
+    r.blocks50 = (hS[b].k + 49) / 50;
+    r.status = hS[b].status ? MCG_WNOTCONV : MCG_OK;
+    r.pad_ = 0;
+    if (r.status) worst = MCG_WNOTCONV;
+  }
+  return worst;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *mcg_status_string(mcg_status s) {
+  switch (s) {
+  case MCG_OK: return "ok";
+  case MCG_WNOTCONV: return "not converged within max_sweeps";
+  case MCG_EINVAL: return "invalid argument";
+  case MCG_ENOMEM: return "out of device memory";
+  case MCG_EHIP: return "HIP runtime error";
+  case MCG_EINPUT: return "input outside the supported range";
+  default: return "unknown status";
+  }
+}
+
+const char *mcg_last_error(const mcg_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+mcg_status mcg_create(mcg_ctx **out, int32_t device) {
+  if (!out) return MCG_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return MCG_EHIP;
+  }
+  if (hipSetDevice(device) != hipSuccess) return MCG_EHIP;
+  mcg_ctx *ctx = new mcg_ctx();
+  ctx->device = device;
+  *out = ctx;
+  return MCG_OK;
+}
+
+mcg_status mcg_destroy(mcg_ctx *ctx) {
+  if (!ctx) return MCG_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  DevBuf *bufs[] = {&ctx->part, &ctx->scalars, &ctx->counts, &ctx->states, &ctx->desc, &ctx->tmpfield,
+                    &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part};
+  for (DevBuf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (auto *v : {&ctx->W, &ctx->fpart, &ctx->traj})
+    for (DevBuf &b : *v)
+      if (b.p) (void)hipFree(b.p);
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  delete ctx;
+  return MCG_OK;
+}
+
+size_t mcg_field_bytes(mcg_dims d, int32_t prec) {
+  if (prec != MCG_F64 && prec != MCG_F32) return 0;
+  return field_bytes(d, prec);
+}
+
+size_t mcg_gauge_bytes(mcg_dims d) {
+  if (!dims_valid(d)) return 0;
+  return (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3] * 9 * 2 * sizeof(double);
+}
+
+mcg_status mcg_pack_links(mcg_ctx *ctx, const void *src, int32_t src_prec, mcg_field *dst, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st = check_field(ctx, dst, "dst");
+  if (st) return st;
+  if (!src || (src_prec != MCG_F64 && src_prec != MCG_F32)) return fail(ctx, MCG_EINVAL, "bad source");
+  const Geom g = geom_of(dst->d);
+  hipStream_t s = (hipStream_t)stream;
+  if (src_prec == MCG_F64 && dst->prec == MCG_F64) HIPCHK((launch_pack_links<double, double>(g, src, dst->ptr, s)));
+  if (src_prec == MCG_F64 && dst->prec == MCG_F32) HIPCHK((launch_pack_links<double, float>(g, src, dst->ptr, s)));
+  if (src_prec == MCG_F32 && dst->prec == MCG_F32) HIPCHK((launch_pack_links<float, float>(g, src, dst->ptr, s)));
+  if (src_prec == MCG_F32 && dst->prec == MCG_F64) HIPCHK((launch_pack_links<float, double>(g, src, dst->ptr, s)));
+  return MCG_OK;
+}
+
+mcg_status mcg_unpack_links(mcg_ctx *ctx, const mcg_field *src, void *dst, int32_t dst_prec, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st = check_field(ctx, src, "src");
+  if (st) return st;
+  if (!dst || (dst_prec != MCG_F64 && dst_prec != MCG_F32)) return fail(ctx, MCG_EINVAL, "bad destination");
+  const Geom g = geom_of(src->d);
+  hipStream_t s = (hipStream_t)stream;
+  if (src->prec == MCG_F64 && dst_prec == MCG_F64) HIPCHK((launch_unpack_links<double, double>(g, src->ptr, dst, s)));
+  if (src->prec == MCG_F64 && dst_prec == MCG_F32) HIPCHK((launch_unpack_links<double, float>(g, src->ptr, dst, s)));
+  if (src->prec == MCG_F32 && dst_prec == MCG_F32) HIPCHK((launch_unpack_links<float, float>(g, src->ptr, dst, s)));
+  if (src->prec == MCG_F32 && dst_prec == MCG_F64) HIPCHK((launch_unpack_links<float, double>(g, src->ptr, dst, s)));
+  return MCG_OK;
+}
+
+mcg_status mcg_pack_gauge(mcg_ctx *ctx, const double *src, mcg_gauge *dst, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!src || !dst || !dst->ptr || !dims_valid(dst->d)) return fail(ctx, MCG_EINVAL, "bad gauge arguments");
+  HIPCHK(launch_pack_gauge(geom_of(dst->d), src, dst->ptr, (hipStream_t)stream));
+  return MCG_OK;
+}
+
+mcg_status mcg_unpack_gauge(mcg_ctx *ctx, const mcg_gauge *src, double *dst, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!src || !dst || !src->ptr || !dims_valid(src->d)) return fail(ctx, MCG_EINVAL, "bad gauge arguments");
+  HIPCHK(launch_unpack_gauge(geom_of(src->d), src->ptr, dst, (hipStream_t)stream));
+  return MCG_OK;
+}
+
+mcg_status mcg_gauge_identity(mcg_ctx *ctx, mcg_gauge *G, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!G || !G->ptr || !dims_valid(G->d)) return fail(ctx, MCG_EINVAL, "bad gauge argument");
+  HIPCHK(launch_gauge_identity(geom_of(G->d), G->ptr, (hipStream_t)stream));
+  return MCG_OK;
+}
+
+mcg_status mcg_gauge_reunit(mcg_ctx *ctx, mcg_gauge *G, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!G || !G->ptr || !dims_valid(G->d)) return fail(ctx, MCG_EINVAL, "bad gauge argument");
+  HIPCHK(launch_gauge_reunit(geom_of(G->d), G->ptr, (hipStream_t)stream));
+  return MCG_OK;
+}
+
+mcg_status mcg_smear(mcg_ctx *ctx, const mcg_field *U, mcg_field *out, double rho, double eps, int32_t n,
+                     void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, out, "out"))) return st;
+  if (!same_dims(U->d, out->d) || U->prec != out->prec)
+    return fail(ctx, MCG_EINVAL, "U and out differ in extents or precision");
+  if (U->ptr == out->ptr) return fail(ctx, MCG_EINVAL, "U and out must not alias");
+  if (n < 0 || std::isnan(rho) || std::isnan(eps)) return fail(ctx, MCG_EINVAL, "bad smearing parameters");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = field_bytes(U->d, U->prec);
+  if (n == 0) {
+    HIPCHK(hipMemcpyAsync(out->ptr, U->ptr, bytes, hipMemcpyDeviceToDevice, s));
+    return MCG_OK;
+  }
+  if (n > 1 && (st = ensure(ctx, ctx->tmpfield, bytes))) return st;
+  const Geom g = geom_of(U->d);
+  // ping-pong so that the last step writes `out`
+  const void *src = U->ptr;
+  for (int k = 0; k < n; k++) {
+    void *dst = ((n - 1 - k) % 2 == 0) ? out->ptr : ctx->tmpfield.p;
+    if (U->prec == MCG_F64)
+      HIPCHK(launch_smear_step<double>(g, src, dst, rho, eps, s));
+    else
+      HIPCHK(launch_smear_step<float>(g, src, dst, rho, eps, s));
+    src = dst;
+  }
+  return MCG_OK;
+}
+
+mcg_status mcg_apply_gauge(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, mcg_field *out,
+                           void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, out, "out")) ||
+      (st = check_gauge(ctx, G, U->d, "G")))
+    return st;
+  if (!same_dims(U->d, out->d) || U->prec != out->prec)
+    return fail(ctx, MCG_EINVAL, "U and out differ in extents or precision");
+  const Geom g = geom_of(U->d);
+  if (U->prec == MCG_F64)
+    HIPCHK(launch_apply_gauge<double>(g, U->ptr, G->ptr, out->ptr, (hipStream_t)stream));
+  else
+    HIPCHK(launch_apply_gauge<float>(g, U->ptr, G->ptr, out->ptr, (hipStream_t)stream));
+  return MCG_OK;
+}
+
+static mcg_status field_scalar(mcg_ctx *ctx, const mcg_field *U, double *out, void *stream, int what) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U"))) return st;
+  if (!out) return fail(ctx, MCG_EINVAL, "NULL output");
+  const Geom g = geom_of(U->d);
+  if ((st = ensure(ctx, ctx->part, sizeof(double) * field_blocks256(g))) ||
+      (st = ensure(ctx, ctx->scalars, 64)))
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  double *dres = (double *)ctx->scalars.p;
+  if (what == 0) {
+    if (U->prec == MCG_F64) HIPCHK(launch_functional<double>(g, U->ptr, (double *)ctx->part.p, dres, s));
+    else HIPCHK(launch_functional<float>(g, U->ptr, (double *)ctx->part.p, dres, s));
+  } else {
+    if (U->prec == MCG_F64) HIPCHK(launch_plaquette<double>(g, U->ptr, (double *)ctx->part.p, dres, s));
+    else HIPCHK(launch_plaquette<float>(g, U->ptr, (double *)ctx->part.p, dres, s));
+  }
+  HIPCHK(hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MCG_OK;
+}
+
+mcg_status mcg_functional(mcg_ctx *ctx, const mcg_field *U, double *R, void *stream) {
+  return field_scalar(ctx, U, R, stream, 0);
+}
+
+mcg_status mcg_plaquette(mcg_ctx *ctx, const mcg_field *U, double *P, void *stream) {
+  return field_scalar(ctx, U, P, stream, 1);
+}
+
+}  // extern "C"
+
+template <typename T>
+static mcg_status theta_impl(mcg_ctx *ctx, const mcg_field *W, double *theta, hipStream_t s) {
+  const Geom g = geom_of(W->d);
+  const int bs = 256, nb = nblocks(g, bs);
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->part, sizeof(double) * nb)) || (st = ensure(ctx, ctx->states, sizeof(FixState))) ||
+      (st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) ||
+      (st = ensure_pinned(ctx, sizeof(LatDesc<T>) + sizeof(FixState))))
+    return st;
+  LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
+  memset(hD, 0, sizeof(LatDesc<T>));
+  hD->g = g;
+  hD->blk0 = 0;
+  hD->nblk = nb;
+  hD->W = (V2<T> *)W->ptr;
+  hD->st = (FixState *)ctx->states.p;
+  hD->part = (double *)ctx->part.p;
+  HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_theta<T>(bs, ctx->desc.p, 1, nb, s));
+  HIPCHK(launch_book<T>(ctx->desc.p, 1, BOOK_THETA, s));
+  FixState *hS = (FixState *)(hD + 1);
+  HIPCHK(hipMemcpyAsync(hS, ctx->states.p, sizeof(FixState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *theta = hS->theta;
+  return MCG_OK;
+}
+
+extern "C" {
+
+
+mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, W, "W"))) return st;
+  if (!theta) return fail(ctx, MCG_EINVAL, "NULL output");
+  return W->prec == MCG_F64 ? theta_impl<double>(ctx, W, theta, (hipStream_t)stream)
+                            : theta_impl<float>(ctx, W, theta, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+template <typename T>
+static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int parity, double omega,
+                                 hipStream_t s) {
+  const Geom g = geom_of(W->d);
+  const int variant = ctx->variant[W->prec], nb = nblocks(g, variant_block(variant));
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
+    return st;
+  // the pinned staging area may still feed an earlier copy on this stream
+  HIPCHK(hipStreamSynchronize(s));
+  LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
+  memset(hD, 0, sizeof(LatDesc<T>));
+  hD->g = g;
+  hD->nblk = nb;
+  hD->W = (V2<T> *)W->ptr;
+  hD->G = (double2 *)G->ptr;
+  HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, parity, omega, false, false, s));
+  return MCG_OK;
+}
+
+extern "C" {
+
+
+mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parity, double omega, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, W, "W")) || (st = check_gauge(ctx, G, W->d, "G"))) return st;
+  if (parity != 0 && parity != 1) return fail(ctx, MCG_EINVAL, "parity must be 0 or 1");
+  if (!(omega >= 0.0 && omega <= 2.0)) return fail(ctx, MCG_EINVAL, "omega must lie in [0, 2]");
+  return W->prec == MCG_F64 ? halfsweep_impl<double>(ctx, W, G, parity, omega, (hipStream_t)stream)
+                            : halfsweep_impl<float>(ctx, W, G, parity, omega, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+template <typename T>
+static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best, double *ms, hipStream_t s) {
+  const Geom g = geom_of(U->d);
+  const size_t fb = field_bytes(U->d, U->prec), gb = mcg_gauge_bytes(U->d);
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->tmpfield, fb)) || (st = ensure(ctx, ctx->grad_a, gb)) ||
+      (st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
+    return st;
+  HIPCHK(hipMemcpyAsync(ctx->tmpfield.p, U->ptr, fb, hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
+  HIPCHK(hipStreamSynchronize(s));
+  LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double tbest = 1e300;
+  int vbest = ctx->variant[U->prec];
+  mcg_status rc = MCG_OK;
+  for (int v = 0; v < NUM_VARIANTS && rc == MCG_OK; v++) {
+    const int nb = nblocks(g, variant_block(v));
+    memset(hD, 0, sizeof(LatDesc<T>));
+    hD->g = g;
+    hD->nblk = nb;
+    hD->W = (V2<T> *)ctx->tmpfield.p;
+    hD->G = (double2 *)ctx->grad_a.p;
+    hipError_t e = hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    for (int k = 0; k < 4 && e == hipSuccess; k++)
+      e = launch_halfsweep<T>(v, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    const int reps = 8;
+    for (int k = 0; k < reps && e == hipSuccess; k++)
+      e = launch_halfsweep<T>(v, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(ctx, MCG_EHIP, "autotune variant %d: %s", v, hipGetErrorString(e));
+      break;
+    }
+    const double per = (double)t / reps;
+    if (ms) ms[v] = per;
+    if (per < tbest) {
+      tbest = per;
+      vbest = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->variant[U->prec] = vbest;
+  if (best) *best = vbest;
+  return MCG_OK;
+}
+
+extern "C" {
+
+mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant, double *ms_per_halfsweep,
+                        void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U"))) return st;
+  return U->prec == MCG_F64 ? autotune_impl<double>(ctx, U, best_variant, ms_per_halfsweep, (hipStream_t)stream)
+                            : autotune_impl<float>(ctx, U, best_variant, ms_per_halfsweep, (hipStream_t)stream);
+}
+
+mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant) {
+  if (!ctx) return MCG_EINVAL;
+  if ((prec != MCG_F64 && prec != MCG_F32) || variant < 0 || variant >= NUM_VARIANTS)
+    return fail(ctx, MCG_EINVAL, "bad precision or variant");
+  ctx->variant[prec] = variant;
+  return MCG_OK;
+}
+
+mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant) {
+  if (!ctx) return MCG_EINVAL;
+  if ((prec != MCG_F64 && prec != MCG_F32) || !variant) return fail(ctx, MCG_EINVAL, "bad arguments");
+  *variant = ctx->variant[prec];
+  return MCG_OK;
+}
+
+mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix_opts *opts,
+                   mcg_fix_result *res, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!U) return fail(ctx, MCG_EINVAL, "U is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  return U->prec == MCG_F64 ? fix_impl<double>(ctx, 1, U, G, opts, res, s, false)
+                            : fix_impl<float>(ctx, 1, U, G, opts, res, s, false);
+}
+
+mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge *G,
+                         const mcg_fix_opts *opts, mcg_fix_result *res, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!U || B < 1) return fail(ctx, MCG_EINVAL, "empty batch");
+  hipStream_t s = (hipStream_t)stream;
+  return U[0].prec == MCG_F64 ? fix_impl<double>(ctx, B, U, G, opts, res, s, true)
+                              : fix_impl<float>(ctx, B, U, G, opts, res, s, true);
+}
+
+mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, int8_t *Z,
+                              double *min_margin, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U"))) return st;
+  if (G && (st = check_gauge(ctx, G, U->d, "G"))) return st;
+  if (!Z) return fail(ctx, MCG_EINVAL, "Z is NULL");
+  const Geom g = geom_of(U->d);
+  if ((st = ensure(ctx, ctx->part, sizeof(double) * field_blocks256(g))) ||
+      (st = ensure(ctx, ctx->scalars, 64)))
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  const double *gp = G ? G->ptr : nullptr;
+  double *dmin = (double *)ctx->scalars.p + 1;
+  if (U->prec == MCG_F64)
+    HIPCHK(launch_center_project<double>(g, U->ptr, gp, Z, (double *)ctx->part.p, dmin, s));
+  else
+    HIPCHK(launch_center_project<float>(g, U->ptr, gp, Z, (double *)ctx->part.p, dmin, s));
+  if (min_margin) {
+    HIPCHK(hipMemcpyAsync(min_margin, dmin, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return MCG_OK;
+}
+
+mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t *total, int64_t *per_plane,
+                              int64_t *per_charge, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  if (!Z || !total) return fail(ctx, MCG_EINVAL, "NULL argument");
+  if (!dims_valid(d)) return fail(ctx, MCG_EINVAL, "bad extents");
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->counts, 12 * sizeof(unsigned long long)))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemsetAsync(ctx->counts.p, 0, 12 * sizeof(unsigned long long), s));
+  HIPCHK(launch_count_vortices(geom_of(d), Z, (unsigned long long *)ctx->counts.p, s));
+  unsigned long long h[12];
+  HIPCHK(hipMemcpyAsync(h, ctx->counts.p, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t tot = 0;
+  for (int p = 0; p < 6; p++) {
+    const int64_t a = (int64_t)h[2 * p], b = (int64_t)h[2 * p + 1];
+    if (per_plane) per_plane[p] = a + b;
+    tot += a + b;
+  }
+  if (per_charge) {
+    per_charge[0] = per_charge[1] = 0;
+    for (int p = 0; p < 6; p++) {
+      per_charge[0] += (int64_t)h[2 * p];
+      per_charge[1] += (int64_t)h[2 * p + 1];
+    }
+  }
+  *total = tot;
+  return MCG_OK;
+}
+
+mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int32_t n,
+                                  const mcg_gauge *Gstar, int32_t ckpt_every, mcg_field *gradU, double *loss,
+                                  double *dRho, double *dEps, void *stream) {
+  (void)U; (void)rho; (void)eps; (void)n; (void)Gstar; (void)ckpt_every; (void)gradU;
+  (void)loss; (void)dRho; (void)dEps; (void)stream;
+  return fail(ctx, MCG_EINVAL, "mcg_smear_mcg_backward is not available in this build");
+}
+
+}  // extern "C"

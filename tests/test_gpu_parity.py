@@ -1,0 +1,256 @@
+"""Parity of the gfx950 path with the FP64 oracle, element by element, on
+seeded inputs: lattices spanning several blocks with ragged tails, plus the
+smallest (2^4) case.  FP64 to 1e-12 (relative where stated), FP32 to 1e-5
+(the oracle is fed the FP32-rounded values); centre integers and vortex
+counts bit-exact wherever the centre-phase margin exceeds 1e-4."""
+import numpy as np
+import pytest
+
+from helpers import center_links, gauge_transform, planted_field
+
+pytestmark = pytest.mark.gpu
+
+LATS = [(4, 4, 4, 4), (6, 4, 4, 8), (6, 6, 6, 10), (2, 2, 2, 2)]
+PRECS = [0, 1]
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import gpu_util
+    return gpu_util
+
+
+@pytest.fixture(scope="module")
+def api(g):
+    from paper_0807_0264_amd import api as a
+    for prec in (0, 1):
+        a.set_variant(prec, 2)
+    return a
+
+
+def field(S, L, seed, sweeps=5):
+    return S.heatbath_field(L, S.sub_seed(seed), 5.7, sweeps)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_pack_roundtrip(S, g, api, L, prec):
+    U = field(S, L, 1000)
+    W = g.links(U, prec)
+    back = g.host_links(W)
+    assert np.array_equal(back, g.rounded(U, prec))
+    G = S.haar_gauge(L, S.sub_seed(1001))
+    assert np.array_equal(g.host_gauge(g.gauge(G)), G)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_apply_gauge_functional_plaquette(S, O, g, api, L, prec):
+    U = g.rounded(field(S, L, 1002), prec)
+    G = S.haar_gauge(L, S.sub_seed(1003))
+    Wd = api.apply_gauge(g.links(U, prec), g.gauge(G))
+    want = O.apply_gauge(U, G)
+    assert np.abs(g.host_links(Wd) - want).max() < (1e-14 if prec == 0 else 1e-6)
+    assert abs(api.functional(Wd) - O.functional(want)) <= TOL[prec] * O.functional(want)
+    assert abs(api.plaquette(g.links(U, prec)) - O.plaquette(U)) <= TOL[prec] * abs(O.plaquette(U))
+    assert np.array_equal(g.host_gauge(api.gauge_identity(L)), np.broadcast_to(np.eye(3), G.shape))
+
+
+@pytest.mark.parametrize("eps", [1.0, -0.25])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_smear(S, O, g, api, L, prec, eps):
+    U = g.rounded(field(S, L, 1004), prec)
+    rho = 0.1 if eps == 1.0 else 0.06
+    got = g.host_links(api.smear(g.links(U, prec), rho, eps, 3))
+    want = O.smear(U, rho, eps, 3)
+    assert np.abs(got - want).max() < (1e-13 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_smear_zero_steps_and_zero_rho(S, g, api, prec):
+    L = (6, 4, 4, 8)
+    U = g.rounded(field(S, L, 1005), prec)
+    assert np.array_equal(g.host_links(api.smear(g.links(U, prec), 0.1, 1.0, 0)), U)
+    # rho = 0: C = 0, exp(0) = 1 exactly
+    assert np.array_equal(g.host_links(api.smear(g.links(U, prec), 0.0, -0.25, 2)), U)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_halfsweeps(S, O, g, api, L, prec):
+    U = g.rounded(field(S, L, 1006), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1007))
+    W = g.links(U, prec)
+    Gd = g.gauge(G0)
+    Wo, Go = U.copy(), G0.copy()
+    for par in (0, 1, 0):
+        api.halfsweep(W, Gd, par, 1.7)
+        Wo, Go = O.halfsweep(Wo, Go, par, 1.7)
+    assert np.abs(g.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 2e-5)
+    assert np.abs(g.host_gauge(Gd) - Go).max() < (1e-13 if prec == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_fix_trajectory(S, O, g, api, L, prec):
+    """40 sweeps with re-unitarisation every 7: R after every sweep matches."""
+    U = g.rounded(field(S, L, 1008), prec)
+    G, info = api.fix(g.links(U, prec), None, tol=-1.0, max_sweeps=40, reunit_every=7,
+                      check_every=9, want_traj=True)
+    Go, io, to = O.mcg_fix(U, tol=-1.0, max_sweeps=40, reunit_every=7, want_traj=True)
+    assert info["sweeps"] == io["sweeps"] == 40 and info["status"] == io["status"] == 1
+    rel = np.abs(info["traj"] - to) / to
+    assert rel.max() < TOL[prec]
+    assert abs(info["R"] - io["R"]) <= TOL[prec] * io["R"]
+    if prec == 0:
+        assert np.abs(g.host_gauge(G) - Go).max() < 1e-11
+        assert abs(info["theta"] - io["theta"]) <= 1e-9 * max(io["theta"], 1e-12)
+
+
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 8), (6, 6, 6, 10)])
+def test_fix_to_convergence_fp64(S, O, g, api, L):
+    U = field(S, L, 1009, 20)
+    G, info = api.fix(g.links(U, 0), None, tol=1e-9, max_sweeps=3000, want_traj=True)
+    Go, io, to = O.mcg_fix(U, tol=1e-9, max_sweeps=3000, want_traj=True)
+    assert info["status"] == io["status"] == 0
+    # the stop sweep can differ only if some dR lies within rounding of tol
+    assert abs(info["sweeps"] - io["sweeps"]) <= 1
+    n = min(info["sweeps"], io["sweeps"]) + 1
+    assert (np.abs(info["traj"][:n] - to[:n]) / to[:n]).max() < 1e-12
+    if info["sweeps"] == io["sweeps"]:
+        assert abs(info["R"] - io["R"]) < 1e-12 * io["R"]
+        assert np.abs(g.host_gauge(G) - Go).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", LATS)
+def test_center_project_and_vortices(S, O, g, api, L, prec):
+    U = g.rounded(field(S, L, 1010), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1011))
+    Gfix, _ = api.fix(g.links(U, prec), g.gauge(G0), tol=-1.0, max_sweeps=15)
+    G = g.host_gauge(Gfix)
+    Zd, mmin = api.center_project(g.links(U, prec), Gfix)
+    Z = g.z_interchange(Zd, L)
+    Zo, margin = O.center_project(U, G)
+    safe = margin > 1e-4
+    assert np.array_equal(Z[safe], Zo[safe])
+    assert abs(mmin - margin.min()) < 1e-9
+    # vortex counting is exact integer work: compare on the GPU's own Z
+    vd = api.count_vortices(Zd, L)
+    vo = O.count_vortices(Z)
+    assert vd == {k: vo[k] for k in ("total", "per_plane", "per_charge")}
+    # and on uniformly random Z3 integers
+    m = S.z3_links(L, S.sub_seed(1012))
+    import torch
+    Zr = torch.from_numpy(np.ascontiguousarray(np.moveaxis(m, -1, 0).reshape(4, -1))).cuda()
+    vo = O.count_vortices(m)
+    assert api.count_vortices(Zr, L) == {k: vo[k] for k in ("total", "per_plane", "per_charge")}
+
+
+def test_center_project_without_gauge(S, O, g, api):
+    L = (6, 4, 4, 8)
+    m = S.z3_links(L, S.sub_seed(1013))
+    U = center_links(m)
+    Zd, mmin = api.center_project(g.links(U, 0), None)
+    assert np.array_equal(g.z_interchange(Zd, L), m)
+    assert abs(mmin - np.pi / 3) < 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_planted_pipeline(S, O, g, api, prec):
+    """Planted U = g Z g^dag (4^4): 10 stout steps at rho = 0.1 leave it
+    unchanged, fixing reaches R = 1, and the projected field has exactly
+    the planted vortex count."""
+    L = (4, 4, 4, 4)
+    Up, gp, m = planted_field(S, L, 1014)
+    U = g.links(Up, prec)
+    out = api.precondition_and_fix(U, rho=0.1, eps=1.0, n=10, tol=1e-10 if prec == 0 else 1e-7,
+                                   max_sweeps=5000)
+    assert out["R_smeared"] > 1 - (1e-10 if prec == 0 else 1e-5)
+    assert out["R"] > 1 - (1e-10 if prec == 0 else 1e-5)
+    assert out["vortices"]["total"] == O.count_vortices(m)["total"]
+    assert out["min_margin"] > 1.0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_equals_single(S, g, api, prec):
+    """Each field of a batch (unequal lattices and Gribov copies) gets the bits
+    of its standalone fix."""
+    Ls = [(4, 4, 4, 4), (6, 6, 6, 10), (6, 4, 4, 8), (6, 6, 6, 10)]
+    Us = [g.rounded(field(S, L, 1015 + i), prec) for i, L in enumerate(Ls)]
+    Us[3] = Us[1]  # a second Gribov copy of field 1
+    G0s = [S.haar_gauge(L, S.sub_seed(1020), copy=i) for i, L in enumerate(Ls)]
+    tols = [1e-9, 1e-9, 1e-8, 1e-9] if prec == 0 else [1e-6] * 4
+    Fs = [g.links(U, prec) for U in Us]
+    Gs, infos = api.fix_batch(Fs, [g.gauge(G0) for G0 in G0s], tol=tols, max_sweeps=[400, 300, 400, 250],
+                              reunit_every=20, check_every=25, want_traj=True)
+    for b in range(4):
+        Gb, ib = api.fix(g.links(Us[b], prec), g.gauge(G0s[b]), tol=tols[b],
+                         max_sweeps=[400, 300, 400, 250][b], reunit_every=20, check_every=25,
+                         want_traj=True)
+        assert ib["sweeps"] == infos[b]["sweeps"]
+        assert ib["R"] == infos[b]["R"] and ib["theta"] == infos[b]["theta"]
+        assert np.array_equal(ib["traj"], infos[b]["traj"])
+        assert np.array_equal(g.host_gauge(Gb), g.host_gauge(Gs[b]))
+
+
+def test_resume_is_bitwise(S, g, api):
+    L = (6, 4, 4, 8)
+    U = field(S, L, 1030)
+    Ga, ia = api.fix(g.links(U, 0), None, tol=-1.0, max_sweeps=60, reunit_every=30)
+    Gb, ib = api.fix(g.links(U, 0), None, tol=-1.0, max_sweeps=30, reunit_every=30)
+    assert ib["status"] == 1
+    Gc, ic = api.fix(g.links(U, 0), Gb, tol=-1.0, max_sweeps=30, reunit_every=30, start_sweep=30)
+    assert np.array_equal(g.host_gauge(Ga), g.host_gauge(Gc))
+    assert ia["R"] == ic["R"]
+
+
+def test_invalid_arguments_raise(S, g, api):
+    import torch
+    from paper_0807_0264_amd.api import MCGError, Links
+    L = (4, 4, 4, 4)
+    U = g.links(field(S, L, 1031), 0)
+    bad = Links((5, 4, 4, 4), 0, U.data)
+    with pytest.raises(MCGError, match="even"):
+        api.functional(bad)
+    with pytest.raises(MCGError, match="alias"):
+        api.smear(U, 0.1, 1.0, 2, out=U)
+    with pytest.raises(MCGError, match="omega"):
+        api.fix(U, None, omega=2.5)
+    with pytest.raises(MCGError, match="parity"):
+        api.halfsweep(U, api.gauge_identity(L), 2)
+    # the context stays usable after an error
+    assert 0 < api.functional(U) < 1
+
+
+def test_max_sweeps_zero_and_warning(S, g, api):
+    L = (4, 4, 4, 4)
+    U = g.links(field(S, L, 1032), 0)
+    G, info = api.fix(U, None, tol=1e-12, max_sweeps=0)
+    assert info["sweeps"] == 0 and info["status"] == 1
+    G, info = api.fix(U, None, tol=1e-12, max_sweeps=3)
+    assert info["sweeps"] == 3 and info["status"] == 1 and info["blocks50"] == 1
+
+
+def test_autotune_keeps_results_valid(S, g, api):
+    L = (6, 6, 6, 10)
+    U = field(S, L, 1033)
+    best, ms = api.autotune(g.links(U, 1))
+    assert 0 <= best < 6 and all(t > 0 for t in ms)
+    G, info = api.fix(g.links(g.rounded(U, 1), 1), None, tol=-1.0, max_sweeps=10, want_traj=True)
+    api.set_variant(1, 2)
+    G2, info2 = api.fix(g.links(g.rounded(U, 1), 1), None, tol=-1.0, max_sweeps=10, want_traj=True)
+    assert np.abs(info["traj"] - info2["traj"]).max() < 1e-6
+
+
+def test_synth_gpu_is_bitwise_cpu(S, g):
+    for L, n in (((4, 4, 4, 4), 4), ((6, 4, 4, 8), 3)):
+        a = S.heatbath_field(L, S.sub_seed(1040), 5.7, n)
+        b = S.heatbath_field_gpu(L, S.sub_seed(1040), 5.7, n).cpu().numpy()
+        assert np.array_equal(a, b)
+        assert np.array_equal(S.haar_gauge(L, 5, 3), S.haar_gauge_gpu(L, 5, 3).cpu().numpy())
