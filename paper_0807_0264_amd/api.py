@@ -72,6 +72,10 @@ class Links:
     data: torch.Tensor
 
     def abi(self):
+        need = A.load().mcg_field_bytes(_dims(self.L), self.prec)
+        have = self.data.numel() * self.data.element_size()
+        if need == 0 or have < need:
+            raise ValueError(f"link buffer of {have} bytes, the field needs {need}")
         f = A.Field()
         f.d = _dims(self.L)
         f.prec = self.prec
@@ -92,6 +96,10 @@ class GaugeField:
     data: torch.Tensor  # float64, V * 18 reals
 
     def abi(self):
+        need = A.load().mcg_gauge_bytes(_dims(self.L))
+        have = self.data.numel() * self.data.element_size()
+        if need == 0 or have < need:
+            raise ValueError(f"gauge buffer of {have} bytes, the field needs {need}")
         g = A.Gauge()
         g.d = _dims(self.L)
         g.ptr = self.data.data_ptr()
@@ -113,12 +121,19 @@ def empty_links(L, prec, device=None):
     prec = _prec_of(prec)
     dt = torch.float64 if prec == A.MCG_F64 else torch.float32
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-    return Links(tuple(int(v) for v in L), prec, torch.empty(volume(L) * 36, dtype=dt, device=dev))
+    nbytes = A.load().mcg_field_bytes(_dims(L), prec)
+    if nbytes == 0:
+        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2")
+    return Links(tuple(int(v) for v in L), prec,
+                 torch.empty(nbytes // torch.empty((), dtype=dt).element_size(), dtype=dt, device=dev))
 
 
 def empty_gauge(L, device=None):
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
-    return GaugeField(tuple(int(v) for v in L), torch.empty(volume(L) * 18, dtype=torch.float64, device=dev))
+    nbytes = A.load().mcg_gauge_bytes(_dims(L))
+    if nbytes == 0:
+        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2")
+    return GaugeField(tuple(int(v) for v in L), torch.empty(nbytes // 8, dtype=torch.float64, device=dev))
 
 
 def dims_of_interchange(U):

@@ -133,8 +133,9 @@ mcg_status check_gauge(mcg_ctx *ctx, const mcg_gauge *G, const mcg_dims &d, cons
 
 size_t field_bytes(const mcg_dims &d, int prec) {
   if (!dims_valid(d)) return 0;
+  // 4 links x 9 complex entries x 2 reals per site
   size_t V = (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3];
-  return V * 36 * (prec == MCG_F64 ? sizeof(double) : sizeof(float));
+  return V * 72 * (prec == MCG_F64 ? sizeof(double) : sizeof(float));
 }
 
 int nblocks(const Geom &g, int bs) { return (g.Vh + bs - 1) / bs; }

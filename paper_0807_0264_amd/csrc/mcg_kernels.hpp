@@ -1,0 +1,261 @@
+// mcg_kernels.hpp -- kernels of the fixing iteration (launchers in k_mcg.hip).
+#pragma once
+
+#include "fix_types.hpp"
+#include "internal.hpp"
+
+namespace mcg {
+
+template <typename T>
+__device__ __forceinline__ int find_field(const LatDesc<T> *__restrict__ D, int B) {
+  int b = 0;
+  for (int i = 1; i < B; i++)
+    if ((int)blockIdx.x >= D[i].blk0) b = i;
+  return b;
+}
+
+// ---------------------------------------------------------- local update
+// One SU(2) subgroup step on rows/columns (I, J): the subgroup element
+// s = a0 + i a.sigma maximising Re tr(s Y) is a* = v/|v| with
+// v = (Re(y11+y22), -Im(y12+y21), Re(y21-y12), -Im(y11-y22)); it is
+// over-relaxed to a = normalise((1-omega) e0 + omega a*) and applied from
+// the left to Y and g.
+template <typename T, int I, int J, bool UPDATE_Y>
+__device__ __forceinline__ void su2_step(M3<T> &Y, M3<T> &g, T omega) {
+  const cx<T> y11 = Y.e[4 * I], y12 = Y.e[3 * I + J], y21 = Y.e[3 * J + I], y22 = Y.e[4 * J];
+  const T v0 = y11.re + y22.re, v1 = -(y12.im + y21.im);
+  const T v2 = y21.re - y12.re, v3 = -(y11.im - y22.im);
+  const T n2 = v0 * v0 + v1 * v1 + v2 * v2 + v3 * v3;
+  if (!(n2 > T(0))) return;
+  const T inv = T(1) / sqrt(n2);
+  T a0 = (T(1) - omega) + omega * (v0 * inv);
+  T a1 = omega * (v1 * inv), a2 = omega * (v2 * inv), a3 = omega * (v3 * inv);
+  const T na2 = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+  if (!(na2 > T(0))) return;
+  const T ia = T(1) / sqrt(na2);
+  a0 *= ia;
+  a1 *= ia;
+  a2 *= ia;
+  a3 *= ia;
+  const cx<T> s00{a0, a3}, s01{a2, a1}, s10{-a2, a1}, s11{a0, -a3};
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    if (UPDATE_Y) {
+      const cx<T> yi = Y.e[3 * I + c], yj = Y.e[3 * J + c];
+      Y.e[3 * I + c] = s00 * yi + s01 * yj;
+      Y.e[3 * J + c] = s10 * yi + s11 * yj;
+    }
+    const cx<T> gi = g.e[3 * I + c], gj = g.e[3 * J + c];
+    g.e[3 * I + c] = s00 * gi + s01 * gj;
+    g.e[3 * J + c] = s10 * gi + s11 * gj;
+  }
+}
+
+// g from the linearisation X = sum_k conj(tr M_k) M_k: subgroups (0,1), (1,2), (0,2)
+template <typename T> __device__ __forceinline__ M3<T> local_update(M3<T> Y, T omega) {
+  M3<T> g = m_ident<T>();
+  su2_step<T, 0, 1, true>(Y, g, omega);
+  su2_step<T, 1, 2, true>(Y, g, omega);
+  su2_step<T, 0, 2, false>(Y, g, omega);
+  return g;
+}
+
+// X += t * B^dagger
+template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3<T> &b, M3<T> &X) {
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) X.e[3 * i + j] = X.e[3 * i + j] + t * conj(b.e[3 * j + i]);
+}
+
+// ----------------------------------------------------------- half-sweep
+// Every site x of parity `par` gathers its eight links (forward W_mu(x),
+// backward W_mu(x-mu)^dag), builds X, g, and writes g W_mu(x),
+// W_mu(x-mu) g^dag and g G(x).  Sites of one parity share no link, so the
+// update is race-free.  With WR, per-block sums of |tr W|^2 over the eight
+// written links are stored; on the odd half-sweep these cover every link of
+// the lattice once (each link joins one even and one odd site).
+template <typename T, int BS, bool WR, int OCC>
+__global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
+                                                  T omega, int gated) {
+  const int b = find_field(D, B);
+  const LatDesc<T> d = D[b];
+  if (gated && d.st->done) return;
+  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  double r = 0.0;
+  if (h < d.g.Vh) {
+    const Links<T> W{d.W, d.g.Vh};
+    const Gauge G{d.G, d.g.Vh};
+    int c[4];
+    coords_of(d.g, par, h, c);
+    const unsigned of = W.off(par, h);
+    unsigned ob[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+      int e[4];
+      moved(d.g, c, mu, -1, e);
+      ob[mu] = W.off(1 - par, half_index(d.g, e));
+    }
+    M3<T> F[4], Bk[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) F[mu] = W.load_off(mu, of);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) Bk[mu] = W.load_off(mu, ob[mu]);
+
+    M3<T> X = m_zero<T>();
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) axpy(conj(trace(F[mu])), F[mu], X);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) axpy_dag(trace(Bk[mu]), Bk[mu], X);
+    const M3<T> g = local_update<T>(X, omega);
+
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+      const M3<T> f = mul(g, F[mu]);
+      W.store_off(mu, of, f);
+      if (WR) r += tr2(f);
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+      const M3<T> bk = mul_nd(Bk[mu], g);
+      W.store_off(mu, ob[mu], bk);
+      if (WR) r += tr2(bk);
+    }
+    G.store(par, h, mul(m_cvt<double>(g), G.load(par, h)));
+  }
+  if (WR) {
+    const double s = block_sum<BS>(r);
+    if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+  }
+}
+
+// W = U^G (FP64 products, rounded once), with per-block sums of |tr W|^2.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ D, int B, int gated) {
+  const int b = find_field(D, B);
+  const LatDesc<T> d = D[b];
+  if (gated && d.st->done) return;
+  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  double r = 0.0;
+  if (h < d.g.Vh) {
+    const Links<T> W{d.W, d.g.Vh}, U{const_cast<V2<T> *>(d.U), d.g.Vh};
+    const Gauge G{d.G, d.g.Vh};
+    for (int par = 0; par < 2; par++) {
+      int c[4];
+      coords_of(d.g, par, h, c);
+      const M3<double> Gx = G.load(par, h);
+#pragma unroll
+      for (int mu = 0; mu < 4; mu++) {
+        int e[4];
+        moved(d.g, c, mu, +1, e);
+        const M3<double> Gn = G.load(1 - par, half_index(d.g, e));
+        const M3<T> w = m_cvt<T>(mul_nd(mul(Gx, m_cvt<double>(U.load(mu, par, h))), Gn));
+        W.store(mu, par, h, w);
+        r += tr2(w);
+      }
+    }
+  }
+  const double s = block_sum<BS>(r);
+  if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_reunit(const LatDesc<T> *__restrict__ D, int B, int gated) {
+  const int b = find_field(D, B);
+  const LatDesc<T> d = D[b];
+  if (gated && d.st->done) return;
+  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  if (h >= d.g.Vh) return;
+  const Gauge G{d.G, d.g.Vh};
+  for (int par = 0; par < 2; par++) {
+    M3<double> m = G.load(par, h);
+    reunit(m);
+    G.store(par, h, m);
+  }
+}
+
+// (1/V) sum_x |TA X(x)|^2 partials (both parities; X as in the half-sweep)
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_theta(const LatDesc<T> *__restrict__ D, int B) {
+  const int b = find_field(D, B);
+  const LatDesc<T> d = D[b];
+  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  double r = 0.0;
+  if (h < d.g.Vh) {
+    const Links<T> W{d.W, d.g.Vh};
+    for (int par = 0; par < 2; par++) {
+      int c[4];
+      coords_of(d.g, par, h, c);
+      M3<T> X = m_zero<T>();
+#pragma unroll
+      for (int mu = 0; mu < 4; mu++) {
+        const M3<T> f = W.load(mu, par, h);
+        axpy(conj(trace(f)), f, X);
+      }
+#pragma unroll
+      for (int mu = 0; mu < 4; mu++) {
+        int e[4];
+        moved(d.g, c, mu, -1, e);
+        const M3<T> bk = W.load(mu, 1 - par, half_index(d.g, e));
+        axpy_dag(trace(bk), bk, X);
+      }
+      const M3<T> t = ta(X);
+      r += (double)rdot(t, t);
+    }
+  }
+  const double s = block_sum<BS>(r);
+  if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+}
+
+// ------------------------------------------------------ bookkeeping
+// One block per field (grid = B).  R is normalised as (1/(9 N_l)) sum |tr|^2.
+enum { BK_INIT = 0, BK_RESET = 1, BK_CHECK = 2, BK_FINAL = 3, BK_THETA = 4 };
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, int what) {
+  const LatDesc<T> d = D[blockIdx.x];
+  FixState *st = d.st;
+  if ((what == BK_RESET || what == BK_CHECK) && st->done) return;
+  const double s = sum_partials<256>(d.part, d.nblk);
+  if (threadIdx.x != 0) return;
+  const double R = s / (9.0 * (double)(4 * d.g.V));
+  switch (what) {
+  case BK_INIT:
+    st->R_prev = R;
+    st->R_last = R;
+    st->dR = 0.0;
+    st->k = 0;
+    st->done = st->max_k <= 0 ? 1 : 0;
+    st->status = 1;
+    if (d.traj) d.traj[0] = R;
+    break;
+  case BK_RESET:
+    st->R_prev = R;
+    break;
+  case BK_CHECK: {
+    const double dR = R - st->R_prev;
+    st->k += 1;
+    st->dR = dR;
+    st->R_last = R;
+    if (d.traj) d.traj[st->k] = R;
+    if (dR < st->tol) {
+      st->done = 1;
+      st->status = 0;
+    } else if (st->k >= st->max_k) {
+      st->done = 1;
+      st->status = 1;
+    } else {
+      st->R_prev = R;
+    }
+    break;
+  }
+  case BK_FINAL:
+    st->R_final = R;
+    break;
+  default:  // BK_THETA
+    st->theta = s / (double)d.g.V;
+    break;
+  }
+}
+
+}  // namespace mcg

@@ -1,0 +1,31 @@
+// smear_kernels.hpp -- the smearing-step kernel (launcher in k_smear.hip).
+#pragma once
+
+#include "internal.hpp"
+#include "smear.hpp"
+
+namespace mcg {
+
+template <typename T, bool OI>
+__global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__ U,
+                                               V2<T> *__restrict__ out, T rho, T wp, T wr) {
+  const int h = blockIdx.x * 128 + threadIdx.x;
+  if (h >= g.Vh) return;
+  const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
+  const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+  int c[4];
+  coords_of(g, par, h, c);
+  M3<T> Cp, Cr;
+  staples<T, OI>(g, L, c, mu, Cp, Cr);
+  M3<T> C;
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    C.e[k] = rho * (wp * Cp.e[k]);
+    if (OI) C.e[k] = rho * (wp * Cp.e[k] + wr * Cr.e[k]);
+  }
+  const M3<T> u = L.load(mu, par, h);
+  const M3<T> E = exp_su3(ta(mul_nd(C, u)));
+  Links<T>{out, g.Vh}.store(mu, par, h, mul(E, u));
+}
+
+}  // namespace mcg

@@ -1,0 +1,218 @@
+"""The library's C ABI driven with numpy buffers as device memory, for the
+host-emulation build (libmcg_emu.so).  Mirrors paper_0807_0264_amd.api.
+Test infrastructure only."""
+import ctypes as C
+import os
+
+import numpy as np
+
+from paper_0807_0264_amd import _abi as A
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libmcg_emu.so")
+
+_lib = None
+_ctx = None
+
+
+def lib():
+    global _lib, _ctx
+    if _lib is None:
+        A._lib = None
+        _lib = A.load(LIB)
+        h = C.c_void_p()
+        assert _lib.mcg_create(C.byref(h), 0) == 0
+        _ctx = h
+    return _lib
+
+
+def ctx():
+    lib()
+    return _ctx
+
+
+class MCGError(RuntimeError):
+    pass
+
+
+def check(st, allow_warn=False):
+    if st == 0 or (allow_warn and st == 1):
+        return st
+    raise MCGError(f"{lib().mcg_last_error(ctx()).decode()} (status {st})")
+
+
+def ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def dims(L):
+    d = A.Dims()
+    for k in range(4):
+        d.L[k] = int(L[k])
+    return d
+
+
+def V(L):
+    return int(L[0] * L[1] * L[2] * L[3])
+
+
+class Links:
+    def __init__(self, L, prec, data=None):
+        self.L, self.prec = tuple(L), prec
+        self.data = data if data is not None else np.zeros(V(L) * 72, np.float64 if prec == 0 else np.float32)
+
+    def abi(self):
+        f = A.Field()
+        f.d = dims(self.L)
+        f.prec = self.prec
+        f.ptr = self.data.ctypes.data
+        return f
+
+
+class Gauge:
+    def __init__(self, L, data=None):
+        self.L = tuple(L)
+        self.data = data if data is not None else np.zeros(V(L) * 18, np.float64)
+
+    def abi(self):
+        g = A.Gauge()
+        g.d = dims(self.L)
+        g.ptr = self.data.ctypes.data
+        return g
+
+
+def L_of(U):
+    return (U.shape[3], U.shape[2], U.shape[1], U.shape[0])
+
+
+def links(U, prec):
+    U = np.ascontiguousarray(U, np.complex128)
+    out = Links(L_of(U), prec)
+    f = out.abi()
+    check(lib().mcg_pack_links(ctx(), ptr(U), 0, C.byref(f), None))
+    return out
+
+
+def host_links(W):
+    out = np.empty((W.L[3], W.L[2], W.L[1], W.L[0], 4, 3, 3), np.complex128)
+    f = W.abi()
+    check(lib().mcg_unpack_links(ctx(), C.byref(f), ptr(out), 0, None))
+    return out
+
+
+def gauge(G):
+    G = np.ascontiguousarray(G, np.complex128)
+    out = Gauge((G.shape[3], G.shape[2], G.shape[1], G.shape[0]))
+    g = out.abi()
+    check(lib().mcg_pack_gauge(ctx(), ptr(G), C.byref(g), None))
+    return out
+
+
+def host_gauge(Gd):
+    out = np.empty((Gd.L[3], Gd.L[2], Gd.L[1], Gd.L[0], 3, 3), np.complex128)
+    g = Gd.abi()
+    check(lib().mcg_unpack_gauge(ctx(), C.byref(g), ptr(out), None))
+    return out
+
+
+def gauge_identity(L):
+    G = Gauge(L)
+    g = G.abi()
+    check(lib().mcg_gauge_identity(ctx(), C.byref(g), None))
+    return G
+
+
+def apply_gauge(U, G):
+    out = Links(U.L, U.prec)
+    fu, g, fo = U.abi(), G.abi(), out.abi()
+    check(lib().mcg_apply_gauge(ctx(), C.byref(fu), C.byref(g), C.byref(fo), None))
+    return out
+
+
+def _scalar(fn, U):
+    f = U.abi()
+    v = C.c_double()
+    check(fn(ctx(), C.byref(f), C.byref(v), None))
+    return v.value
+
+
+def functional(U):
+    return _scalar(lib().mcg_functional, U)
+
+
+def plaquette(U):
+    return _scalar(lib().mcg_plaquette, U)
+
+
+def theta(U):
+    return _scalar(lib().mcg_theta, U)
+
+
+def smear(U, rho, eps, n):
+    out = Links(U.L, U.prec)
+    fu, fo = U.abi(), out.abi()
+    check(lib().mcg_smear(ctx(), C.byref(fu), C.byref(fo), rho, eps, n, None))
+    return out
+
+
+def halfsweep(W, G, par, omega=1.7):
+    f, g = W.abi(), G.abi()
+    check(lib().mcg_halfsweep(ctx(), C.byref(f), C.byref(g), par, omega, None))
+
+
+def _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj):
+    o = A.FixOpts()
+    o.tol, o.omega, o.max_sweeps = tol, omega, max_sweeps
+    o.reunit_every, o.start_sweep, o.check_every = reunit_every, start_sweep, check_every
+    o.traj = traj.ctypes.data_as(C.POINTER(C.c_double)) if traj is not None else None
+    return o
+
+
+def fix(U, G=None, tol=1e-7, max_sweeps=100, omega=1.7, reunit_every=50, start_sweep=0, check_every=10,
+        want_traj=True):
+    G = G if G is not None else gauge_identity(U.L)
+    traj = np.zeros(max_sweeps + 1) if want_traj else None
+    o = _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj)
+    r = A.FixResult()
+    fu, g = U.abi(), G.abi()
+    check(lib().mcg_fix(ctx(), C.byref(fu), C.byref(g), C.byref(o), C.byref(r), None), allow_warn=True)
+    info = dict(R=r.R, dR=r.dR, theta=r.theta, sweeps=r.sweeps, status=r.status)
+    if traj is not None:
+        info["traj"] = traj[: r.sweeps + 1].copy()
+    return G, info
+
+
+def fix_batch(Us, Gs, tols, maxs, omega=1.7, reunit_every=50, check_every=10):
+    B = len(Us)
+    trajs = [np.zeros(m + 1) for m in maxs]
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    GG = (A.Gauge * B)(*[G.abi() for G in Gs])
+    O = (A.FixOpts * B)(*[_opts(tols[b], maxs[b], omega, reunit_every, 0, check_every, trajs[b])
+                          for b in range(B)])
+    R = (A.FixResult * B)()
+    check(lib().mcg_fix_batch(ctx(), B, F, GG, O, R, None), allow_warn=True)
+    return [dict(R=R[b].R, theta=R[b].theta, sweeps=R[b].sweeps, status=R[b].status,
+                 traj=trajs[b][: R[b].sweeps + 1].copy()) for b in range(B)]
+
+
+def center_project(U, G=None):
+    Z = np.zeros((4, V(U.L)), np.int8)
+    f = U.abi()
+    g = G.abi() if G is not None else None
+    mm = C.c_double()
+    check(lib().mcg_center_project(ctx(), C.byref(f), C.byref(g) if g is not None else None, ptr(Z),
+                                   C.byref(mm), None))
+    return Z, mm.value
+
+
+def count_vortices(Z, L):
+    tot = C.c_int64()
+    pp = (C.c_int64 * 6)()
+    pc = (C.c_int64 * 2)()
+    check(lib().mcg_count_vortices(ctx(), ptr(np.ascontiguousarray(Z)), dims(L), C.byref(tot), pp, pc, None))
+    return dict(total=tot.value, per_plane=list(pp), per_charge=list(pc))
+
+
+def z_interchange(Z, L):
+    z = Z.reshape(4, L[3], L[2], L[1], L[0])
+    return np.ascontiguousarray(np.moveaxis(z, 0, -1))

@@ -1,0 +1,143 @@
+"""Run the library's kernels and driver, built for the host against the
+emulated HIP runtime (libmcg_emu.so, AddressSanitizer + UBSan), through the
+C ABI on small seeded lattices, and compare with the FP64 oracle.  Any
+out-of-bounds access aborts the process.  Started by tests/test_emu.py in a
+subprocess with libasan preloaded.  Test infrastructure only."""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path[:0] = [ROOT, os.path.dirname(HERE), HERE]
+
+import emu_api as E  # noqa: E402
+from helpers import center_links, planted_field  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+from paper_0807_0264_amd import synth as S  # noqa: E402
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def rounded(U, prec):
+    return U if prec == 0 else U.astype(np.complex64).astype(np.complex128)
+
+
+def field(L, seed, sweeps=3):
+    return S.heatbath_field(L, S.sub_seed(seed), 5.7, sweeps)
+
+
+def check(cond, what):
+    if not cond:
+        raise AssertionError(what)
+
+
+def scenario_fields(L, prec):
+    U = rounded(field(L, 2000), prec)
+    G = S.haar_gauge(L, S.sub_seed(2001))
+    W = E.links(U, prec)
+    check(np.array_equal(E.host_links(W), U), "pack/unpack")
+    check(np.array_equal(E.host_gauge(E.gauge(G)), G), "gauge pack/unpack")
+    Wd = E.apply_gauge(W, E.gauge(G))
+    want = O.apply_gauge(U, G)
+    check(np.abs(E.host_links(Wd) - want).max() < (1e-14 if prec == 0 else 1e-6), "apply_gauge")
+    check(abs(E.functional(Wd) - O.functional(want)) <= TOL[prec] * O.functional(want), "functional")
+    check(abs(E.plaquette(W) - O.plaquette(U)) <= TOL[prec] * abs(O.plaquette(U)), "plaquette")
+    check(np.array_equal(E.host_gauge(E.gauge_identity(L)), np.broadcast_to(np.eye(3), G.shape)), "identity")
+
+
+def scenario_smear(L, prec):
+    U = rounded(field(L, 2002), prec)
+    for eps, rho in ((1.0, 0.1), (-0.25, 0.06)):
+        got = E.host_links(E.smear(E.links(U, prec), rho, eps, 2))
+        want = O.smear(U, rho, eps, 2)
+        check(np.abs(got - want).max() < (1e-13 if prec == 0 else 1e-5), f"smear eps={eps}")
+
+
+def scenario_halfsweep(L, prec):
+    U = rounded(field(L, 2003), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(2004))
+    W, Gd = E.links(U, prec), E.gauge(G0)
+    Wo, Go = U.copy(), G0.copy()
+    for par in (0, 1):
+        E.halfsweep(W, Gd, par)
+        Wo, Go = O.halfsweep(Wo, Go, par, 1.7)
+    check(np.abs(E.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 2e-5), "halfsweep links")
+    check(np.abs(E.host_gauge(Gd) - Go).max() < (1e-13 if prec == 0 else 2e-5), "halfsweep gauge")
+
+
+def scenario_fix(L, prec):
+    U = rounded(field(L, 2005), prec)
+    G, info = E.fix(E.links(U, prec), None, tol=-1.0, max_sweeps=9, reunit_every=4, check_every=3)
+    Go, io, to = O.mcg_fix(U, tol=-1.0, max_sweeps=9, reunit_every=4, want_traj=True)
+    check(info["sweeps"] == io["sweeps"] == 9, "sweep count")
+    check((np.abs(info["traj"] - to) / to).max() < TOL[prec], "trajectory")
+    check(abs(info["R"] - io["R"]) <= TOL[prec] * io["R"], "final R")
+    if prec == 0:
+        check(np.abs(E.host_gauge(G) - Go).max() < 1e-11, "final G")
+        check(abs(info["theta"] - io["theta"]) <= 1e-9 * max(io["theta"], 1e-12), "theta")
+
+
+def scenario_project(L, prec):
+    U = rounded(field(L, 2006), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(2007))
+    Gf, _ = E.fix(E.links(U, prec), E.gauge(G0), tol=-1.0, max_sweeps=4)
+    G = E.host_gauge(Gf)
+    Zd, mmin = E.center_project(E.links(U, prec), Gf)
+    Z = E.z_interchange(Zd, L)
+    Zo, margin = O.center_project(U, G)
+    safe = margin > 1e-4
+    check(np.array_equal(Z[safe], Zo[safe]), "centre integers")
+    check(abs(mmin - margin.min()) < 1e-9, "min margin")
+    vo = O.count_vortices(Z)
+    check(E.count_vortices(Zd, L) == {k: vo[k] for k in ("total", "per_plane", "per_charge")}, "vortices")
+    m = S.z3_links(L, S.sub_seed(2008))
+    Zr = np.ascontiguousarray(np.moveaxis(m, -1, 0).reshape(4, -1))
+    vo = O.count_vortices(m)
+    check(E.count_vortices(Zr, L) == {k: vo[k] for k in ("total", "per_plane", "per_charge")}, "random Z3")
+    Zc, mc = E.center_project(E.links(center_links(m), 0), None)
+    check(np.array_equal(E.z_interchange(Zc, L), m) and abs(mc - np.pi / 3) < 1e-12, "centre field")
+
+
+def scenario_batch(prec):
+    Ls = [(4, 4, 4, 4), (6, 4, 4, 2), (2, 2, 2, 2)]
+    Us = [rounded(field(L, 2010 + i), prec) for i, L in enumerate(Ls)]
+    G0s = [S.haar_gauge(L, S.sub_seed(2020), copy=i) for i, L in enumerate(Ls)]
+    maxs, tols = [9, 7, 5], [1e-12, 1e-12, 1e-12]
+    infos = E.fix_batch([E.links(U, prec) for U in Us], [E.gauge(G) for G in G0s], tols, maxs,
+                        reunit_every=3, check_every=2)
+    for b in range(3):
+        _, ib = E.fix(E.links(Us[b], prec), E.gauge(G0s[b]), tol=tols[b], max_sweeps=maxs[b],
+                      reunit_every=3, check_every=2)
+        check(ib["sweeps"] == infos[b]["sweeps"], "batch sweeps")
+        check(ib["R"] == infos[b]["R"] and np.array_equal(ib["traj"], infos[b]["traj"]), "batch bits")
+
+
+def scenario_planted():
+    L = (4, 4, 4, 4)
+    Up, gp, m = planted_field(S, L, 2030)
+    G, info = E.fix(E.links(Up, 0), None, tol=1e-12, max_sweeps=200, check_every=20)
+    check(info["R"] > 1 - 1e-10, f"planted R {info['R']}")
+    Zd, _ = E.center_project(E.links(Up, 0), G)
+    check(E.count_vortices(Zd, L)["total"] == O.count_vortices(m)["total"], "planted vortex count")
+
+
+def main():
+    lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
+    names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted"]
+    for name in names:
+        if name == "batch":
+            for prec in (0, 1):
+                scenario_batch(prec)
+        elif name == "planted":
+            scenario_planted()
+        else:
+            for L in lat:
+                for prec in (0, 1):
+                    globals()["scenario_" + name](L, prec)
+        print("ok", name, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -42,3 +42,21 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _abi.load(str(tmp_path / "absent.so"))
         finally:
             _abi._lib = None
+
+
+def test_buffer_sizes():
+    """A link field holds 4 links x 9 complex entries per site, a gauge field
+    9 complex entries per site (host-only calls, no device needed)."""
+    from paper_0807_0264_amd import _abi
+    if not os.path.exists(_abi.LIBPATH):
+        pytest.skip("libmcg.so not built")
+    lib = _abi.load()
+    d = _abi.Dims()
+    for k, v in enumerate((6, 4, 2, 8)):
+        d.L[k] = v
+    V = 6 * 4 * 2 * 8
+    assert lib.mcg_field_bytes(d, _abi.MCG_F64) == V * 4 * 9 * 2 * 8
+    assert lib.mcg_field_bytes(d, _abi.MCG_F32) == V * 4 * 9 * 2 * 4
+    assert lib.mcg_gauge_bytes(d) == V * 9 * 2 * 8
+    d.L[1] = 5
+    assert lib.mcg_field_bytes(d, _abi.MCG_F64) == 0 and lib.mcg_gauge_bytes(d) == 0
