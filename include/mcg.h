@@ -170,6 +170,11 @@ mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stre
  * W_mu(x-mu) <- W_mu(x-mu) g^dagger, G(x) <- g G(x).  W and G must not alias. */
 mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parity,
                          double omega, void *stream);
+/* n raw sweeps in place: n times (every even site, then every odd site) as
+ * in mcg_halfsweep, launched back to back with no stop test, no R and no
+ * re-unitarisation (the fixed-work loop used to measure throughput). */
+mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
+                      void *stream);
 /* Fix U to MCG.  G holds the start transform on entry (mcg_gauge_identity for
  * plain fixing; the smeared field's transform for the preconditioned re-fix)
  * and the total transform on exit; U is not modified.  The working field

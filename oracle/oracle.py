@@ -209,6 +209,12 @@ def halfsweep(W, G, parity, omega):
     return W, G
 
 
+def halfsweep_inplace(W, G, parity, omega):
+    """One half-sweep applied in place to contiguous complex128 arrays."""
+    assert W.dtype == np.complex128 and W.flags.c_contiguous and G.flags.c_contiguous
+    lib().or_halfsweep(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega)
+
+
 def theta(W):
     W = _c128(W)
     return lib().or_theta(_dims(dims_of(W)), _ptr(W))

@@ -63,6 +63,7 @@ SIGNATURES = {
     "mcg_plaquette": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_double), _P]),
     "mcg_theta": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_double), _P]),
     "mcg_halfsweep": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.c_int32, C.c_double, _P]),
+    "mcg_sweeps": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.c_int32, C.c_double, _P]),
     "mcg_fix": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.POINTER(FixOpts),
                      C.POINTER(FixResult), _P]),
     "mcg_fix_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(Gauge),

@@ -74,7 +74,9 @@ class Links:
     def abi(self):
         need = A.load().mcg_field_bytes(_dims(self.L), self.prec)
         have = self.data.numel() * self.data.element_size()
-        if need == 0 or have < need:
+        if need == 0:
+            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2")
+        if have < need:
             raise ValueError(f"link buffer of {have} bytes, the field needs {need}")
         f = A.Field()
         f.d = _dims(self.L)
@@ -98,7 +100,9 @@ class GaugeField:
     def abi(self):
         need = A.load().mcg_gauge_bytes(_dims(self.L))
         have = self.data.numel() * self.data.element_size()
-        if need == 0 or have < need:
+        if need == 0:
+            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2")
+        if have < need:
             raise ValueError(f"gauge buffer of {have} bytes, the field needs {need}")
         g = A.Gauge()
         g.d = _dims(self.L)
@@ -239,6 +243,14 @@ def halfsweep(W, G, parity, omega=1.7):
     ctx = context(W.data.device.index)
     f, g = W.abi(), G.abi()
     _check(A.load().mcg_halfsweep(ctx, C.byref(f), C.byref(g), int(parity), float(omega), _stream()), ctx)
+
+
+def sweeps(W, G, n, omega=1.7):
+    """n raw sweeps (even then odd half-sweep) in place: no stop test, no R,
+    no re-unitarisation.  For throughput measurements."""
+    ctx = context(W.data.device.index)
+    f, g = W.abi(), G.abi()
+    _check(A.load().mcg_sweeps(ctx, C.byref(f), C.byref(g), int(n), float(omega), _stream()), ctx)
 
 
 def _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj):

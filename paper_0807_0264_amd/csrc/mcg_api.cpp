@@ -570,9 +570,10 @@ mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stre
 
 }  // extern "C"
 
+// parity < 0: n full sweeps (0, 1, 0, 1, ...); otherwise one half-sweep of that parity
 template <typename T>
 static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int parity, double omega,
-                                 hipStream_t s) {
+                                 hipStream_t s, int n = 1) {
   const Geom g = geom_of(W->d);
   const int variant = ctx->variant[W->prec], nb = nblocks(g, variant_block(variant));
   mcg_status st;
@@ -587,7 +588,12 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   hD->W = (V2<T> *)W->ptr;
   hD->G = (double2 *)G->ptr;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
-  HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, parity, omega, false, false, s));
+  if (parity >= 0) {
+    HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, parity, omega, false, false, s));
+  } else {
+    for (int k = 0; k < 2 * n; k++)
+      HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, k & 1, omega, false, false, s));
+  }
   return MCG_OK;
 }
 
@@ -687,6 +693,17 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant) {
   if ((prec != MCG_F64 && prec != MCG_F32) || !variant) return fail(ctx, MCG_EINVAL, "bad arguments");
   *variant = ctx->variant[prec];
   return MCG_OK;
+}
+
+mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, W, "W")) || (st = check_gauge(ctx, G, W->d, "G"))) return st;
+  if (n < 0) return fail(ctx, MCG_EINVAL, "n < 0");
+  if (!(omega >= 0.0 && omega <= 2.0)) return fail(ctx, MCG_EINVAL, "omega must lie in [0, 2]");
+  if (n == 0) return MCG_OK;
+  return W->prec == MCG_F64 ? halfsweep_impl<double>(ctx, W, G, -1, omega, (hipStream_t)stream, n)
+                            : halfsweep_impl<float>(ctx, W, G, -1, omega, (hipStream_t)stream, n);
 }
 
 mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix_opts *opts,
