@@ -127,19 +127,22 @@ def cpu_baseline(U64, target_s=15.0):
 
 
 def profile_run(api, torch, synth):
-    """Fixed work for rocprofv3: a plain copy of known size (to calibrate the
-    byte counters), then 20 sweeps at 32^3x64 FP32."""
+    """Fixed work for rocprofv3: plain device copies of known size (to
+    calibrate the byte counters), then 20 sweeps at 32^3x64 FP32 in the
+    benchmark's launch configuration (autotuned variant)."""
     L = LATTICES[0]
-    U = api.to_links(synth.haar_links_gpu(L, 1), 1)
-    n = 256 * 1024 * 1024 // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(5, 0), 5.7, 50), 1)
+    best, _ = api.autotune(U)
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)  # 1 GiB read + 1 GiB written per copy
     W, G = U.clone(), api.gauge_identity(L)
     api.sweeps(W, G, 20)
     torch.cuda.synchronize()
-    print(json.dumps(dict(profile="done", copy_bytes_each_way=4 * n, halfsweeps=40, lattice=L)))
+    print(json.dumps(dict(profile="done", copy_bytes_each_way=nbytes, halfsweeps=40, lattice=L,
+                          variant=best)))
 
 
 def main():

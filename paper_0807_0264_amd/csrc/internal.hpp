@@ -57,13 +57,18 @@ hipError_t launch_center_project(const Geom &g, const void *U, const double *G, 
 hipError_t launch_count_vortices(const Geom &g, const int8_t *Z, unsigned long long *counts,
                                  hipStream_t s);
 
-// k_backward.hip -- adjoint of one smearing step and the loss seed
+// k_backward.hip -- adjoint of one smearing step and the loss seed.
+// Seed: per-block sums of |tr W|^2 into part (field_blocks256 entries).
+// Step: per-block (dL/drho, dL/deps) pairs into part[0 .. 2 nb) and, for
+// eps = 1, the rectangle part of dL/deps into part[2 nb .. 3 nb), with
+// nb = adjoint_blocks(g); *flag is set if an exponent lies outside the
+// range of the unscaled series.
+int adjoint_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
-                            double *loss_out, hipStream_t s);
+                            hipStream_t s);
 template <typename T>
-hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU,
-                               void *gC, double rho, double eps, double *part2,
-                               double *sums_out, hipStream_t s);
+hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, double rho,
+                               double eps, double *part, int *flag, hipStream_t s);
 
 }  // namespace mcg

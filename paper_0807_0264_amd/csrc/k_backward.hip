@@ -1,0 +1,48 @@
+// k_backward.hip -- launchers of the smeared-field functional's adjoint
+// (kernels in backward_kernels.hpp).
+
+#include "backward_kernels.hpp"
+
+namespace mcg {
+
+int adjoint_blocks(const Geom &g) { return 8 * ((g.Vh + 127) / 128); }
+
+template <typename T>
+hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
+                            hipStream_t s) {
+  k_loss_seed<T><<<field_blocks256(g), 256, 0, s>>>(g, (const V2<T> *)S, (const double2 *)G, (V2<T> *)grad,
+                                                     part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, double rho,
+                               double eps, double *part, int *flag, hipStream_t s) {
+  const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
+  dim3 grid((g.Vh + 127) / 128, 8);
+  const int nb = (int)(grid.x * grid.y);
+  if (eps == 1.0) {
+    k_step_adj_a<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gOut, (V2<T> *)gU,
+                                                (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
+    k_eps_rect<T><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (T)rho, part + 2 * nb);
+    k_step_adj_b<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
+                                                (T)wp, (T)wr);
+  } else {
+    k_step_adj_a<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gOut, (V2<T> *)gU,
+                                               (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
+    k_step_adj_b<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
+                                               (T)wp, (T)wr);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_loss_seed<float>(const Geom &, const void *, const double *, void *, double *,
+                                            hipStream_t);
+template hipError_t launch_loss_seed<double>(const Geom &, const void *, const double *, void *, double *,
+                                             hipStream_t);
+template hipError_t launch_step_adjoint<float>(const Geom &, const void *, const void *, void *, void *, double,
+                                               double, double *, int *, hipStream_t);
+template hipError_t launch_step_adjoint<double>(const Geom &, const void *, const void *, void *, void *, double,
+                                                double, double *, int *, hipStream_t);
+
+}  // namespace mcg

@@ -332,6 +332,87 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   return worst;
 }
 
+// ----------------------------------------------------------------- backward
+// L = R(S_n(U)^G*): forward with a checkpoint every c steps, seed grad_S_n,
+// then per segment (last first) recompute the c fields from the checkpoint
+// and apply the step adjoints in reverse.  Partial sums of L, dL/drho and
+// dL/deps stay on the device until the end and are added on the host in a
+// fixed order.
+template <typename T>
+mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int n, const mcg_gauge *Gstar,
+                         int ckpt_every, mcg_field *gradU, double *loss, double *dRho, double *dEps,
+                         hipStream_t s) {
+  const Geom g = geom_of(U->d);
+  const size_t fb = field_bytes(U->d, U->prec);
+  const int c = (ckpt_every <= 0 || ckpt_every > n) ? std::max(n, 1) : ckpt_every;
+  const int nck = n > 0 ? (n + c - 1) / c : 0;
+  // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C
+  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 5;
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->ckpt, fb * nfields))) return st;
+  const int nb_seed = field_blocks256(g), nb_step = adjoint_blocks(g);
+  const size_t nparts = (size_t)nb_seed + (size_t)std::max(n, 1) * 3 * nb_step;
+  if ((st = ensure(ctx, ctx->bw_part, sizeof(double) * nparts + 64))) return st;
+  char *base = (char *)ctx->ckpt.p;
+  auto slot = [&](size_t i) { return (void *)(base + i * fb); };
+  void *tmp0 = slot(nck + c - 1), *tmp1 = slot(nck + c), *gA = slot(nck + c + 1), *gB = slot(nck + c + 2),
+       *gC = slot(nck + c + 3);
+  double *part = (double *)ctx->bw_part.p;
+  int *flag = (int *)(part + nparts);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+  HIPCHK(hipMemsetAsync(part, 0, sizeof(double) * nparts, s));
+
+  // forward, keeping every c-th field
+  const void *cur = U->ptr;
+  for (int k = 0; k < n; k++) {
+    if (k % c == 0) HIPCHK(hipMemcpyAsync(slot(k / c), cur, fb, hipMemcpyDeviceToDevice, s));
+    void *nxt = (cur == tmp0) ? tmp1 : tmp0;
+    HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s));
+    cur = nxt;
+  }
+  HIPCHK(launch_loss_seed<T>(g, cur, Gstar->ptr, gA, part, s));
+  void *gin = gA, *gout = gB;
+  for (int seg = nck - 1; seg >= 0; seg--) {
+    const int k0 = seg * c, len = std::min(c, n - k0);
+    std::vector<const void *> fields(len);
+    fields[0] = slot(seg);
+    for (int j = 1; j < len; j++) {
+      void *dst = slot(nck + j - 1);
+      HIPCHK(launch_smear_step<T>(g, fields[j - 1], dst, rho, eps, s));
+      fields[j] = dst;
+    }
+    for (int j = len - 1; j >= 0; j--) {
+      const int k = k0 + j;
+      double *p = part + nb_seed + (size_t)k * 3 * nb_step;
+      HIPCHK(launch_step_adjoint<T>(g, fields[j], gin, gout, gC, rho, eps, p, flag, s));
+      std::swap(gin, gout);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(gradU->ptr, gin, fb, hipMemcpyDeviceToDevice, s));
+  std::vector<double> h(nparts);
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(h.data(), part, sizeof(double) * nparts, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflag)
+    return fail(ctx, MCG_EINPUT, "a smearing exponent exceeds the range of the adjoint's series "
+                                 "(spectral radius of C U^dag above 4)");
+  double L = 0.0, dr = 0.0, de = 0.0;
+  for (int b = 0; b < nb_seed; b++) L += h[b];
+  for (int k = 0; k < n; k++) {
+    const double *p = h.data() + nb_seed + (size_t)k * 3 * nb_step;
+    for (int b = 0; b < nb_step; b++) {
+      dr += p[2 * b];
+      de += p[2 * b + 1];
+    }
+    for (int b = 0; b < nb_step; b++) de += p[2 * nb_step + b];
+  }
+  *loss = L / (9.0 * (double)(4 * g.V));
+  *dRho = dr;
+  *dEps = de;
+  return MCG_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -782,9 +863,21 @@ mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t
 mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int32_t n,
                                   const mcg_gauge *Gstar, int32_t ckpt_every, mcg_field *gradU, double *loss,
                                   double *dRho, double *dEps, void *stream) {
-  (void)U; (void)rho; (void)eps; (void)n; (void)Gstar; (void)ckpt_every; (void)gradU;
-  (void)loss; (void)dRho; (void)dEps; (void)stream;
-  return fail(ctx, MCG_EINVAL, "mcg_smear_mcg_backward is not available in this build");
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, gradU, "gradU")) ||
+      (st = check_gauge(ctx, Gstar, U->d, "Gstar")))
+    return st;
+  if (!same_dims(U->d, gradU->d) || U->prec != gradU->prec)
+    return fail(ctx, MCG_EINVAL, "U and gradU differ in extents or precision");
+  if (U->ptr == gradU->ptr) return fail(ctx, MCG_EINVAL, "U and gradU must not alias");
+  if (n < 0 || std::isnan(rho) || std::isnan(eps)) return fail(ctx, MCG_EINVAL, "bad smearing parameters");
+  if (!loss || !dRho || !dEps) return fail(ctx, MCG_EINVAL, "NULL output");
+  return U->prec == MCG_F64
+             ? backward_impl<double>(ctx, U, rho, eps, n, Gstar, ckpt_every, gradU, loss, dRho, dEps,
+                                     (hipStream_t)stream)
+             : backward_impl<float>(ctx, U, rho, eps, n, Gstar, ckpt_every, gradU, loss, dRho, dEps,
+                                    (hipStream_t)stream);
 }
 
 }  // extern "C"

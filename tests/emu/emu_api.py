@@ -216,3 +216,12 @@ def count_vortices(Z, L):
 def z_interchange(Z, L):
     z = Z.reshape(4, L[3], L[2], L[1], L[0])
     return np.ascontiguousarray(np.moveaxis(z, 0, -1))
+
+
+def smear_mcg_backward(U, rho, eps, n, G, ckpt_every=2):
+    grad = Links(U.L, U.prec)
+    fu, g, fg = U.abi(), G.abi(), grad.abi()
+    loss, dr, de = C.c_double(), C.c_double(), C.c_double()
+    check(lib().mcg_smear_mcg_backward(ctx(), C.byref(fu), rho, eps, n, C.byref(g), ckpt_every, C.byref(fg),
+                                       C.byref(loss), C.byref(dr), C.byref(de), None))
+    return grad, loss.value, dr.value, de.value

@@ -83,6 +83,12 @@ template <typename T> inline T __shfl_xor(T v, int mask, int width = 64) {
   return r;
 }
 
+inline int atomicOr(int *p, int v) {
+  std::lock_guard<std::mutex> g(emu::atomic_mutex());
+  int o = *p;
+  *p = o | v;
+  return o;
+}
 inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v) {
   std::lock_guard<std::mutex> g(emu::atomic_mutex());
   unsigned long long o = *p;

@@ -123,15 +123,33 @@ def scenario_planted():
     check(E.count_vortices(Zd, L)["total"] == O.count_vortices(m)["total"], "planted vortex count")
 
 
+def scenario_backward(L, prec):
+    U = rounded(field(L, 2040), prec)
+    G = S.haar_gauge(L, S.sub_seed(2041))
+    for rho, eps, n, ck in ((0.1, 1.0, 3, 2), (0.06, -0.25, 3, 1), (0.06, -0.25, 2, 0)):
+        gd, loss, dr, de = E.smear_mcg_backward(E.links(U, prec), rho, eps, n, E.gauge(G), ck)
+        go, dro, deo, losso = O.smear_loss_grad(U, rho, eps, n, G, ckpt_every=ck)
+        tol = 1e-12 if prec == 0 else 1e-5
+        scale = np.abs(go).max()
+        check(np.abs(E.host_links(gd) - go).max() < tol * max(scale, 1e-3) * 10, f"gradU eps={eps}")
+        check(abs(loss - losso) < tol * losso, "loss")
+        check(abs(dr - dro) < tol * max(abs(dro), 1e-3) * 10, f"dRho {dr} {dro}")
+        check(abs(de - deo) < tol * max(abs(deo), 1e-3) * 10, f"dEps {de} {deo}")
+
+
 def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
-    names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted"]
+    names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward"]
     for name in names:
         if name == "batch":
             for prec in (0, 1):
                 scenario_batch(prec)
         elif name == "planted":
             scenario_planted()
+        elif name == "backward":
+            for L in ((4, 4, 4, 4), (2, 2, 2, 2)):
+                for prec in (0, 1):
+                    scenario_backward(L, prec)
         else:
             for L in lat:
                 for prec in (0, 1):
