@@ -154,8 +154,8 @@ def main():
     ap.add_argument("--profile", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the workload is one MI355X's share and no run on "
-              "several GPUs is defined for it (see DESIGN.md for how the path would shard).")
+        print("bench.py measures one GPU: the workload is one MI355X's share of the job, and "
+              "runs on several GPUs are not part of this benchmark.")
         sys.exit(2)
 
     import torch
