@@ -115,7 +115,7 @@ def cpu_baseline(U64, target_s=15.0):
     t0 = time.time()
     O.halfsweep_inplace(W, G, 0, 1.7)
     t1 = time.time() - t0
-    n = max(1, min(40, int(target_s / max(t1, 1e-3)) - 1))
+    n = max(1, min(1000, int(target_s / max(t1, 1e-3)) - 1))
     t0 = time.time()
     for k in range(n):
         O.halfsweep_inplace(W, G, (k + 1) & 1, 1.7)

@@ -38,7 +38,8 @@ def test_backward_vs_oracle(S, O, env, L, prec, rho, eps, n, ck):
     assert np.abs(g.host_links(grad) - go).max() < tol * np.abs(go).max()
     assert abs(loss - losso) < tol * losso
     assert abs(dr - dro) < tol * abs(dro)
-    assert abs(de - deo) < tol * max(abs(deo), 1e-6)
+    # dL/deps can be a near-cancellation of terms of the size of dL/drho
+    assert abs(de - deo) < tol * max(abs(deo), abs(dro))
 
 
 def test_backward_oi20_vs_oracle_6x4(S, O, env):
@@ -122,6 +123,6 @@ def test_autograd_function(S, env):
     Lv = stout_mcg_loss(U, rho, eps, 3, G, 2)
     Lv.backward()
     grad, loss, dr, de = api.smear_mcg_backward(g.links(U0, 0), 0.06, -0.25, 3, G, 2)
-    assert abs(float(Lv) - loss) < 1e-15
+    assert abs(float(Lv.detach()) - loss) < 1e-15
     assert torch.allclose(U.grad, api.from_links(grad, torch.complex128), rtol=0, atol=1e-15)
     assert abs(float(rho.grad) - dr) < 1e-15 and abs(float(eps.grad) - de) < 1e-15
