@@ -29,8 +29,10 @@ METRIC = "MCG site-updates/s and % HBM peak at 32^3x64; batched FP32 vs plain at
 LATTICES = [(32, 32, 32, 64), (24, 24, 24, 48), (20, 20, 20, 40), (16, 16, 16, 16)]
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes of one site-update with FP32 links and an FP64 transform:
-# 8 links read and written (72 B each) + G(x) read and written (144 B)
-BYTES_PER_SITE_UPDATE = 8 * 72 * 2 + 2 * 144
+# 8 links read and written + G(x) read and written.  In the two-row form (the
+# default) a link is 6 complex FP32 (48 B) and G(x) 6 complex FP64 (96 B); as
+# full matrices 72 B and 144 B.
+BYTES_PER_SITE_UPDATE = {True: 8 * 48 * 2 + 2 * 96, False: 8 * 72 * 2 + 2 * 144}
 PMC_FILE = os.path.join(ROOT, "profiles", "halfsweep_pmc_32x32x32x64_fp32.json")
 
 
@@ -77,19 +79,28 @@ def one_step(api, fields, tol=1e-7, max_sweeps=5000):
 
 def roofline(api, torch, U, nsweeps=100):
     """Average duration of the half-sweep kernel at 32^3x64 (FP32 links, FP64
-    G), from HIP events on the stream the kernels are launched on."""
+    G), from HIP events on the stream the kernels are launched on (the
+    library launches on torch's current stream).  A call of api.sweeps also
+    converts W and G to and from the storage form; timing n + 20 and 20
+    sweeps and taking the difference leaves 2n half-sweep launches alone."""
     W = U.clone()
     G = api.gauge_identity(U.L)
     api.sweeps(W, G, 5)  # warm-up
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    api.sweeps(W, G, nsweeps)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / (2 * nsweeps)
+
+    def timed(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.sweeps(W, G, n)
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    ms = (timed(nsweeps + 20) - timed(20)) / (2 * nsweeps)
+    two_row = api.get_two_row()
+    bps = BYTES_PER_SITE_UPDATE[two_row]
     site_updates = api.volume(U.L) // 2
-    achieved = site_updates * BYTES_PER_SITE_UPDATE / (ms * 1e-3) / 1e9
+    achieved = site_updates * bps / (ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(PMC_FILE):
         pmc = json.load(open(PMC_FILE))
@@ -97,9 +108,8 @@ def roofline(api, torch, U, nsweeps=100):
             traffic = pmc.get("hbm_bytes_per_launch")
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_halfsweep<float> (one parity of 32^3x64)", ms_per_launch=round(ms, 4),
-                bytes_per_launch=site_updates * BYTES_PER_SITE_UPDATE,
-                bytes_per_site_update=BYTES_PER_SITE_UPDATE)
+                kernel="k_halfsweep<float,%s> (one parity of 32^3x64)" % ("two-row" if two_row else "full"),
+                ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps)
 
 
 def cpu_baseline(U64, target_s=15.0):

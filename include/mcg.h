@@ -172,7 +172,9 @@ mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parit
                          double omega, void *stream);
 /* n raw sweeps in place: n times (every even site, then every odd site) as
  * in mcg_halfsweep, launched back to back with no stop test, no R and no
- * re-unitarisation (the fixed-work loop used to measure throughput). */
+ * re-unitarisation (the fixed-work loop used to measure throughput).  In the
+ * two-row storage form (MCG_OPT_TWO_ROW) W and G are converted into context
+ * scratch before the sweeps and back after them. */
 mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
                       void *stream);
 /* Fix U to MCG.  G holds the start transform on entry (mcg_gauge_identity for
@@ -195,15 +197,26 @@ mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge 
 /* The half-sweep kernel has MCG_NUM_VARIANTS variants: variant v uses blocks
  * of {64, 128, 256}[v % 3] threads and targets 1 + v / 3 waves per SIMD.
  * mcg_autotune times every variant on a scratch copy of U (G = 1; U is not
- * modified), keeps the fastest for U's precision in the context and returns
- * it (best_variant, ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host).  The
- * variant fixes the block decomposition of every fixing kernel, hence the
- * order of the FP64 partial sums: results at one variant are deterministic. */
+ * modified) in the context's storage form, keeps the fastest for U's
+ * precision and that form, and returns it (best_variant,
+ * ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host).  The variant fixes the
+ * block decomposition of every fixing kernel, hence the order of the FP64
+ * partial sums: results at one variant are deterministic. */
 #define MCG_NUM_VARIANTS 6
 mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant,
                         double *ms_per_halfsweep, void *stream);
 mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant);
 mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
+
+/* ---- options ----------------------------------------------------------------------- */
+/* MCG_OPT_TWO_ROW (default 1): the fixing iteration (mcg_fix, mcg_fix_batch,
+ * mcg_sweeps) keeps its working field W and transform G in context scratch
+ * as their first two rows (row 2 = conj(row 0 x row 1) for SU(3)), moving
+ * 2/3 of the bytes per site-update; 0 keeps all three rows.  Caller-visible
+ * fields and transforms always use the full layouts above. */
+#define MCG_OPT_TWO_ROW 1
+mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value);
+mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value);
 
 /* ---- centre projection and P-vortices (Sec. II.A) -------------------------------- */
 /* Z = centre integer of every link of U^G (G nullable: U as given), decided

@@ -12,6 +12,7 @@ LIBPATH = os.path.join(HERE, "libmcg.so")
 MCG_OK, MCG_WNOTCONV, MCG_EINVAL, MCG_ENOMEM, MCG_EHIP, MCG_EINPUT = 0, 1, -1, -2, -3, -4
 MCG_F64, MCG_F32 = 0, 1
 MCG_NUM_VARIANTS = 6
+MCG_OPT_TWO_ROW = 1
 
 
 class Dims(C.Structure):
@@ -79,6 +80,8 @@ SIGNATURES = {
     "mcg_autotune": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
     "mcg_set_variant": (_S, [_CTX, C.c_int32, C.c_int32]),
     "mcg_get_variant": (_S, [_CTX, C.c_int32, C.POINTER(C.c_int32)]),
+    "mcg_set_option": (_S, [_CTX, C.c_int32, C.c_int32]),
+    "mcg_get_option": (_S, [_CTX, C.c_int32, C.POINTER(C.c_int32)]),
 }
 
 _lib = None

@@ -359,6 +359,19 @@ def set_variant(prec, variant, device=None):
     _check(A.load().mcg_set_variant(ctx, _prec_of(prec), int(variant)), ctx)
 
 
+def set_two_row(on=True, device=None):
+    """Keep the fixing iteration's working field and transform as two rows."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_TWO_ROW, 1 if on else 0), ctx)
+
+
+def get_two_row(device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_TWO_ROW, C.byref(v)), ctx)
+    return bool(v.value)
+
+
 def get_variant(prec, device=None):
     ctx = context(device)
     v = C.c_int32()

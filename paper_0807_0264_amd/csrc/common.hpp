@@ -288,6 +288,101 @@ struct Gauge {
   }
 };
 
+// Make the compiler treat the first two rows of m as freshly produced, so a
+// value derived from them (row 2) is recomputed instead of kept live across a
+// long stretch of code (a register-pressure hint with no run-time cost).
+template <typename T> __device__ __forceinline__ void opaque_rows(M3<T> &m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int k = 0; k < 6; k++) __asm__ volatile("" : "+v"(m.e[k].re), "+v"(m.e[k].im));
+#else
+  (void)m;
+#endif
+}
+
+// ------------------------------------------------- two-row (compressed) I/O
+// An SU(3) matrix is fixed by its first two rows: row 2 = conj(row 0 x row 1).
+// The fixing iteration keeps its working field and transform in this form:
+// 12 reals per matrix instead of 18.
+template <typename T> __device__ __forceinline__ void third_row(M3<T> &m) {
+  m.e[6] = conj(m.e[1] * m.e[5] - m.e[2] * m.e[4]);
+  m.e[7] = conj(m.e[2] * m.e[3] - m.e[0] * m.e[5]);
+  m.e[8] = conj(m.e[0] * m.e[4] - m.e[1] * m.e[3]);
+}
+
+// complex element (mu, par, k < 6, h) at ((mu*2 + par)*6 + k)*Vh + h
+template <typename T> struct Links12 {
+  V2<T> *p;
+  int Vh;
+  __device__ __forceinline__ unsigned off(int par, int h) const {
+    return (unsigned)(par * 6 * Vh + h) * (unsigned)sizeof(V2<T>);
+  }
+  // rows 0 and 1 only (row 2 left unset)
+  __device__ __forceinline__ M3<T> load_rows(int mu, unsigned o) const {
+    M3<T> m;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const V2<T> v = ld_plane(p + (size_t)(mu * 12 + k) * Vh, o);
+      m.e[k] = cx<T>{v.x, v.y};
+    }
+    return m;
+  }
+  __device__ __forceinline__ M3<T> load_off(int mu, unsigned o) const {
+    M3<T> m = load_rows(mu, o);
+    third_row(m);
+    return m;
+  }
+  __device__ __forceinline__ void store_off(int mu, unsigned o, const M3<T> &m) const {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      V2<T> v;
+      v.x = m.e[k].re;
+      v.y = m.e[k].im;
+      st_plane(p + (size_t)(mu * 12 + k) * Vh, o, v);
+    }
+  }
+  __device__ __forceinline__ M3<T> load(int mu, int par, int h) const { return load_off(mu, off(par, h)); }
+  __device__ __forceinline__ void store(int mu, int par, int h, const M3<T> &m) const {
+    store_off(mu, off(par, h), m);
+  }
+};
+
+// complex element (par, k < 6, h) at (par*6 + k)*Vh + h
+struct Gauge12 {
+  double2 *p;
+  int Vh;
+  __device__ __forceinline__ unsigned off(int par, int h) const {
+    return (unsigned)(par * 6 * Vh + h) * (unsigned)sizeof(double2);
+  }
+  __device__ __forceinline__ M3<double> load(int par, int h) const {
+    const unsigned o = off(par, h);
+    M3<double> m;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const double2 v = ld_plane(p + (size_t)k * Vh, o);
+      m.e[k] = cx<double>{v.x, v.y};
+    }
+    third_row(m);
+    return m;
+  }
+  __device__ __forceinline__ void store(int par, int h, const M3<double> &m) const {
+    const unsigned o = off(par, h);
+#pragma unroll
+    for (int k = 0; k < 6; k++) st_plane(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
+  }
+};
+
+// the two storage forms of the fixing iteration's working field and transform
+template <typename T, bool C12> struct FixStore;
+template <typename T> struct FixStore<T, false> {
+  using W = Links<T>;
+  using G = Gauge;
+};
+template <typename T> struct FixStore<T, true> {
+  using W = Links12<T>;
+  using G = Gauge12;
+};
+
 // ------------------------------------------------------------- reductions
 // Deterministic block sum of one double per thread: butterfly within each
 // 64-wide wavefront, then the per-wave sums in wave order.  Result valid in

@@ -15,15 +15,19 @@ namespace mcg {
 constexpr int NUM_VARIANTS = 6;
 inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 256); }
 template <typename T>
-hipError_t launch_halfsweep(int variant, const void *D, int B, int blocks, int par, double omega,
+hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s);
 template <typename T>
-hipError_t launch_rederive(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s);
+hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s);
 template <typename T>
-hipError_t launch_reunit(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s);
+hipError_t launch_reunit(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s);
 template <typename T>
-hipError_t launch_theta(int bs, const void *D, int B, int blocks, hipStream_t s);
+hipError_t launch_theta(int bs, bool c12, const void *D, int B, int blocks, hipStream_t s);
 template <typename T> hipError_t launch_book(const void *D, int B, int what, hipStream_t s);
+// full (18 reals) <-> two-row (12 reals) forms of a link field / gauge field
+template <typename T>
+hipError_t launch_links_form(const Geom &g, const void *src, void *dst, bool to12, hipStream_t s);
+hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool to12, hipStream_t s);
 enum { BOOK_INIT = 0, BOOK_RESET = 1, BOOK_CHECK = 2, BOOK_FINAL = 3, BOOK_THETA = 4 };
 
 // k_field.hip -- layout conversion and whole-field measurements

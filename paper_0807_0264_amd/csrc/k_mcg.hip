@@ -22,46 +22,62 @@ namespace mcg {
   default: return hipErrorInvalidValue;              \
   }
 
-// variant v: block size {64, 128, 256}[v % 3], waves per SIMD 1 + v / 3
+// variant v: block size {64, 128, 256}[v % 3], waves per SIMD 1 + v / 3;
+// c12: working field and transform stored as two rows
 template <typename T>
-hipError_t launch_halfsweep(int variant, const void *D, int B, int blocks, int par, double omega,
+hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
-  if (variant / 3 == 0) {
-    if (withR) {
-      MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, true, 1><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)));
+#define MCG_HS(WR, OCC, C)                                                                         \
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)))
+  if (c12) {
+    if (variant / 3 == 0) {
+      if (withR) { MCG_HS(true, 1, true); } else { MCG_HS(false, 1, true); }
     } else {
-      MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, false, 1><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)));
+      if (withR) { MCG_HS(true, 2, true); } else { MCG_HS(false, 2, true); }
     }
   } else {
-    if (withR) {
-      MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, true, 2><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)));
+    if (variant / 3 == 0) {
+      if (withR) { MCG_HS(true, 1, false); } else { MCG_HS(false, 1, false); }
     } else {
-      MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, false, 2><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)));
+      if (withR) { MCG_HS(true, 2, false); } else { MCG_HS(false, 2, false); }
     }
+  }
+#undef MCG_HS
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s) {
+  const LatDesc<T> *dd = (const LatDesc<T> *)D;
+  if (c12) {
+    MCG_BS_SWITCH(bs, (k_rederive<T, BS, true><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
+  } else {
+    MCG_BS_SWITCH(bs, (k_rederive<T, BS, false><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rederive(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s) {
+hipError_t launch_reunit(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
-  MCG_BS_SWITCH(bs, (k_rederive<T, BS><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
+  if (c12) {
+    MCG_BS_SWITCH(bs, (k_reunit<T, BS, true><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
+  } else {
+    MCG_BS_SWITCH(bs, (k_reunit<T, BS, false><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_reunit(int bs, const void *D, int B, int blocks, bool gated, hipStream_t s) {
+hipError_t launch_theta(int bs, bool c12, const void *D, int B, int blocks, hipStream_t s) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
-  MCG_BS_SWITCH(bs, (k_reunit<T, BS><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_theta(int bs, const void *D, int B, int blocks, hipStream_t s) {
-  const LatDesc<T> *dd = (const LatDesc<T> *)D;
-  MCG_BS_SWITCH(bs, (k_theta<T, BS><<<blocks, BS, 0, s>>>(dd, B)));
+  if (c12) {
+    MCG_BS_SWITCH(bs, (k_theta<T, BS, true><<<blocks, BS, 0, s>>>(dd, B)));
+  } else {
+    MCG_BS_SWITCH(bs, (k_theta<T, BS, false><<<blocks, BS, 0, s>>>(dd, B)));
+  }
   return hipGetLastError();
 }
 
@@ -70,13 +86,27 @@ template <typename T> hipError_t launch_book(const void *D, int B, int what, hip
   return hipGetLastError();
 }
 
-#define MCG_INST(T)                                                                            \
-  template hipError_t launch_halfsweep<T>(int, const void *, int, int, int, double, bool, bool, \
-                                          hipStream_t);                                       \
-  template hipError_t launch_rederive<T>(int, const void *, int, int, bool, hipStream_t);      \
-  template hipError_t launch_reunit<T>(int, const void *, int, int, bool, hipStream_t);        \
-  template hipError_t launch_theta<T>(int, const void *, int, int, hipStream_t);               \
-  template hipError_t launch_book<T>(const void *, int, int, hipStream_t);
+template <typename T>
+hipError_t launch_links_form(const Geom &g, const void *src, void *dst, bool to12, hipStream_t s) {
+  dim3 grid((g.Vh + 255) / 256, 8);
+  k_links_form<T><<<grid, 256, 0, s>>>(g, (const V2<T> *)src, (V2<T> *)dst, to12 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool to12, hipStream_t s) {
+  dim3 grid((g.Vh + 255) / 256, 2);
+  k_gauge_form<<<grid, 256, 0, s>>>(g, (const double2 *)src, (double2 *)dst, to12 ? 1 : 0);
+  return hipGetLastError();
+}
+
+#define MCG_INST(T)                                                                                  \
+  template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
+                                          hipStream_t);                                              \
+  template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
+  template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
+  template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \
+  template hipError_t launch_book<T>(const void *, int, int, hipStream_t);                            \
+  template hipError_t launch_links_form<T>(const Geom &, const void *, void *, bool, hipStream_t);
 MCG_INST(float)
 MCG_INST(double)
 

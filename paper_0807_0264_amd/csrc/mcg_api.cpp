@@ -32,11 +32,12 @@ struct mcg_ctx {
   int device = 0;
   std::string err;
   hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
-  DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part;
-  std::vector<DevBuf> W, fpart, traj;
+  DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part, w12, g12;
+  std::vector<DevBuf> W, G12, fpart, traj;
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
-  int variant[2] = {2, 2};  // half-sweep variant per precision (MCG_F64, MCG_F32)
+  bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
+  int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
 };
 
 namespace {
@@ -140,22 +141,32 @@ size_t field_bytes(const mcg_dims &d, int prec) {
 
 int nblocks(const Geom &g, int bs) { return (g.Vh + bs - 1) / bs; }
 
+// working-field and transform bytes of the fixing iteration in the chosen form
+size_t work_field_bytes(const mcg_dims &d, int prec, bool c12) {
+  return c12 ? field_bytes(d, prec) / 3 * 2 : field_bytes(d, prec);
+}
+size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
+  const size_t V = (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3];
+  return V * (c12 ? 6 : 9) * 2 * sizeof(double);
+}
+
 // ------------------------------------------------------------ fixing driver
 template <typename T> struct FixRun {
   mcg_ctx *ctx;
   hipStream_t s;
   int B, variant, bs, total_blocks;
+  bool c12;
   void *dD;  // device LatDesc table
   double omega;
 
   mcg_status sweep(bool reunit_first) {
     if (reunit_first) {
-      HIPCHK(launch_reunit<T>(bs, dD, B, total_blocks, true, s));
-      HIPCHK(launch_rederive<T>(bs, dD, B, total_blocks, true, s));
+      HIPCHK(launch_reunit<T>(bs, c12, dD, B, total_blocks, true, s));
+      HIPCHK(launch_rederive<T>(bs, c12, dD, B, total_blocks, true, s));
       HIPCHK(launch_book<T>(dD, B, BOOK_RESET, s));
     }
-    HIPCHK(launch_halfsweep<T>(variant, dD, B, total_blocks, 0, omega, false, true, s));
-    HIPCHK(launch_halfsweep<T>(variant, dD, B, total_blocks, 1, omega, true, true, s));
+    HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, total_blocks, 0, omega, false, true, s));
+    HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, total_blocks, 1, omega, true, true, s));
     HIPCHK(launch_book<T>(dD, B, BOOK_CHECK, s));
     return MCG_OK;
   }
@@ -188,9 +199,11 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
       if (U[c].ptr == U[b].ptr && G[c].ptr == G[b].ptr)
         return fail(ctx, MCG_EINVAL, "fields %d and %d share U and G", c, b);
   }
-  const int variant = ctx->variant[prec], bs = variant_block(variant);
+  const bool c12 = ctx->c12;
+  const int variant = ctx->variant[prec][c12], bs = variant_block(variant);
   if ((int)ctx->W.size() < B) {
     ctx->W.resize(B);
+    ctx->G12.resize(B);
     ctx->fpart.resize(B);
     ctx->traj.resize(B);
   }
@@ -204,7 +217,8 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   for (int b = 0; b < B; b++) {
     const Geom g = geom_of(U[b].d);
     const int nb = nblocks(g, bs);
-    if ((st = ensure(ctx, ctx->W[b], field_bytes(U[b].d, prec)))) return st;
+    if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12)))) return st;
+    if (c12 && (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, true)))) return st;
     if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb))) return st;
     const bool want_traj = opts[b].traj != nullptr;
     if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
@@ -214,7 +228,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     d.nblk = nb;
     d.W = (V2<T> *)ctx->W[b].p;
     d.U = (const V2<T> *)U[b].ptr;
-    d.G = (double2 *)G[b].ptr;
+    d.G = c12 ? (double2 *)ctx->G12[b].p : (double2 *)G[b].ptr;
     d.st = (FixState *)ctx->states.p + b;
     d.part = (double *)ctx->fpart[b].p;
     d.traj = want_traj ? (double *)ctx->traj[b].p : nullptr;
@@ -231,8 +245,11 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   // the pinned staging area is reused below: wait for these copies first
   HIPCHK(hipStreamSynchronize(s));
 
-  FixRun<T> run{ctx, s, B, variant, bs, total, ctx->desc.p, omega};
-  HIPCHK(launch_rederive<T>(bs, run.dD, B, total, false, s));
+  FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
+  if (c12)
+    for (int b = 0; b < B; b++)
+      HIPCHK(launch_gauge_form(geom_of(U[b].d), G[b].ptr, (double *)ctx->G12[b].p, true, s));
+  HIPCHK(launch_rederive<T>(bs, c12, run.dD, B, total, false, s));
   HIPCHK(launch_book<T>(run.dD, B, BOOK_INIT, s));
 
   auto all_done = [&](bool &done) -> mcg_status {
@@ -306,11 +323,14 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     }
   }
   // final re-unitarisation, R and the stationarity residual
-  HIPCHK(launch_reunit<T>(bs, run.dD, B, total, false, s));
-  HIPCHK(launch_rederive<T>(bs, run.dD, B, total, false, s));
+  HIPCHK(launch_reunit<T>(bs, c12, run.dD, B, total, false, s));
+  HIPCHK(launch_rederive<T>(bs, c12, run.dD, B, total, false, s));
   HIPCHK(launch_book<T>(run.dD, B, BOOK_FINAL, s));
-  HIPCHK(launch_theta<T>(bs, run.dD, B, total, s));
+  HIPCHK(launch_theta<T>(bs, c12, run.dD, B, total, s));
   HIPCHK(launch_book<T>(run.dD, B, BOOK_THETA, s));
+  if (c12)
+    for (int b = 0; b < B; b++)
+      HIPCHK(launch_gauge_form(geom_of(U[b].d), (const double *)ctx->G12[b].p, G[b].ptr, false, s));
   HIPCHK(hipMemcpyAsync(hS, ctx->states.p, sizeof(FixState) * B, hipMemcpyDeviceToHost, s));
   for (int b = 0; b < B; b++)
     if (opts[b].traj && ctx->traj[b].p)
@@ -452,10 +472,10 @@ mcg_status mcg_destroy(mcg_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   DevBuf *bufs[] = {&ctx->part, &ctx->scalars, &ctx->counts, &ctx->states, &ctx->desc, &ctx->tmpfield,
-                    &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part};
+                    &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part, &ctx->w12, &ctx->g12};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
-  for (auto *v : {&ctx->W, &ctx->fpart, &ctx->traj})
+  for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj})
     for (DevBuf &b : *v)
       if (b.p) (void)hipFree(b.p);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
@@ -628,7 +648,7 @@ static mcg_status theta_impl(mcg_ctx *ctx, const mcg_field *W, double *theta, hi
   hD->st = (FixState *)ctx->states.p;
   hD->part = (double *)ctx->part.p;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
-  HIPCHK(launch_theta<T>(bs, ctx->desc.p, 1, nb, s));
+  HIPCHK(launch_theta<T>(bs, false, ctx->desc.p, 1, nb, s));
   HIPCHK(launch_book<T>(ctx->desc.p, 1, BOOK_THETA, s));
   FixState *hS = (FixState *)(hD + 1);
   HIPCHK(hipMemcpyAsync(hS, ctx->states.p, sizeof(FixState), hipMemcpyDeviceToHost, s));
@@ -651,14 +671,21 @@ mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stre
 
 }  // extern "C"
 
-// parity < 0: n full sweeps (0, 1, 0, 1, ...); otherwise one half-sweep of that parity
+// parity >= 0: one half-sweep of that parity on the caller's (full-form)
+// fields.  parity < 0: n sweeps (0, 1, 0, 1, ...) in the context's storage
+// form; in the two-row form W and G are converted into context scratch,
+// swept, and converted back.
 template <typename T>
 static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int parity, double omega,
                                  hipStream_t s, int n = 1) {
   const Geom g = geom_of(W->d);
-  const int variant = ctx->variant[W->prec], nb = nblocks(g, variant_block(variant));
+  const bool c12 = parity < 0 && ctx->c12;
+  const int variant = ctx->variant[W->prec][c12], nb = nblocks(g, variant_block(variant));
   mcg_status st;
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
+    return st;
+  if (c12 && ((st = ensure(ctx, ctx->w12, work_field_bytes(W->d, W->prec, true))) ||
+              (st = ensure(ctx, ctx->g12, gauge_form_bytes(W->d, true)))))
     return st;
   // the pinned staging area may still feed an earlier copy on this stream
   HIPCHK(hipStreamSynchronize(s));
@@ -666,20 +693,27 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   memset(hD, 0, sizeof(LatDesc<T>));
   hD->g = g;
   hD->nblk = nb;
-  hD->W = (V2<T> *)W->ptr;
-  hD->G = (double2 *)G->ptr;
+  hD->W = c12 ? (V2<T> *)ctx->w12.p : (V2<T> *)W->ptr;
+  hD->G = c12 ? (double2 *)ctx->g12.p : (double2 *)G->ptr;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
-    HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, parity, omega, false, false, s));
-  } else {
-    for (int k = 0; k < 2 * n; k++)
-      HIPCHK(launch_halfsweep<T>(variant, ctx->desc.p, 1, nb, k & 1, omega, false, false, s));
+    HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s));
+    return MCG_OK;
+  }
+  if (c12) {
+    HIPCHK(launch_links_form<T>(g, W->ptr, ctx->w12.p, true, s));
+    HIPCHK(launch_gauge_form(g, G->ptr, (double *)ctx->g12.p, true, s));
+  }
+  for (int k = 0; k < 2 * n; k++)
+    HIPCHK(launch_halfsweep<T>(variant, c12, ctx->desc.p, 1, nb, k & 1, omega, false, false, s));
+  if (c12) {
+    HIPCHK(launch_links_form<T>(g, ctx->w12.p, W->ptr, false, s));
+    HIPCHK(launch_gauge_form(g, (const double *)ctx->g12.p, G->ptr, false, s));
   }
   return MCG_OK;
 }
 
 extern "C" {
-
 
 mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parity, double omega, void *stream) {
   if (!ctx) return MCG_EINVAL;
@@ -697,36 +731,45 @@ mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parit
 template <typename T>
 static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best, double *ms, hipStream_t s) {
   const Geom g = geom_of(U->d);
+  const bool c12 = ctx->c12;
   const size_t fb = field_bytes(U->d, U->prec), gb = mcg_gauge_bytes(U->d);
   mcg_status st;
   if ((st = ensure(ctx, ctx->tmpfield, fb)) || (st = ensure(ctx, ctx->grad_a, gb)) ||
       (st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
     return st;
-  HIPCHK(hipMemcpyAsync(ctx->tmpfield.p, U->ptr, fb, hipMemcpyDeviceToDevice, s));
+  if (c12 && ((st = ensure(ctx, ctx->w12, work_field_bytes(U->d, U->prec, true))) ||
+              (st = ensure(ctx, ctx->g12, gauge_form_bytes(U->d, true)))))
+    return st;
   HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
+  if (c12) {
+    HIPCHK(launch_links_form<T>(g, U->ptr, ctx->w12.p, true, s));
+    HIPCHK(launch_gauge_form(g, (const double *)ctx->grad_a.p, (double *)ctx->g12.p, true, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(ctx->tmpfield.p, U->ptr, fb, hipMemcpyDeviceToDevice, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double tbest = 1e300;
-  int vbest = ctx->variant[U->prec];
+  int vbest = ctx->variant[U->prec][c12];
   mcg_status rc = MCG_OK;
   for (int v = 0; v < NUM_VARIANTS && rc == MCG_OK; v++) {
     const int nb = nblocks(g, variant_block(v));
     memset(hD, 0, sizeof(LatDesc<T>));
     hD->g = g;
     hD->nblk = nb;
-    hD->W = (V2<T> *)ctx->tmpfield.p;
-    hD->G = (double2 *)ctx->grad_a.p;
+    hD->W = c12 ? (V2<T> *)ctx->w12.p : (V2<T> *)ctx->tmpfield.p;
+    hD->G = c12 ? (double2 *)ctx->g12.p : (double2 *)ctx->grad_a.p;
     hipError_t e = hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int k = 0; k < 4 && e == hipSuccess; k++)
-      e = launch_halfsweep<T>(v, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     const int reps = 8;
     for (int k = 0; k < reps && e == hipSuccess; k++)
-      e = launch_halfsweep<T>(v, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
@@ -745,7 +788,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  ctx->variant[U->prec] = vbest;
+  ctx->variant[U->prec][c12] = vbest;
   if (best) *best = vbest;
   return MCG_OK;
 }
@@ -765,15 +808,35 @@ mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant) {
   if (!ctx) return MCG_EINVAL;
   if ((prec != MCG_F64 && prec != MCG_F32) || variant < 0 || variant >= NUM_VARIANTS)
     return fail(ctx, MCG_EINVAL, "bad precision or variant");
-  ctx->variant[prec] = variant;
+  ctx->variant[prec][ctx->c12] = variant;
   return MCG_OK;
 }
 
 mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant) {
   if (!ctx) return MCG_EINVAL;
   if ((prec != MCG_F64 && prec != MCG_F32) || !variant) return fail(ctx, MCG_EINVAL, "bad arguments");
-  *variant = ctx->variant[prec];
+  *variant = ctx->variant[prec][ctx->c12];
   return MCG_OK;
+}
+
+mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
+  if (!ctx) return MCG_EINVAL;
+  if (option == MCG_OPT_TWO_ROW) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_TWO_ROW takes 0 or 1");
+    ctx->c12 = value != 0;
+    return MCG_OK;
+  }
+  return fail(ctx, MCG_EINVAL, "unknown option %d", option);
+}
+
+mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
+  if (!ctx) return MCG_EINVAL;
+  if (!value) return fail(ctx, MCG_EINVAL, "NULL output");
+  if (option == MCG_OPT_TWO_ROW) {
+    *value = ctx->c12 ? 1 : 0;
+    return MCG_OK;
+  }
+  return fail(ctx, MCG_EINVAL, "unknown option %d", option);
 }
 
 mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega, void *stream) {

@@ -75,17 +75,21 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // update is race-free.  With WR, per-block sums of |tr W|^2 over the eight
 // written links are stored; on the odd half-sweep these cover every link of
 // the lattice once (each link joins one even and one odd site).
-template <typename T, int BS, bool WR, int OCC>
+// C12: W and G are stored as their first two rows; only those rows stay in
+// registers and row 2 is rebuilt where a product needs it.
+template <typename T, int BS, bool WR, int OCC, bool C12>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
-                                                  T omega, int gated) {
+                                                       T omega, int gated) {
+  using WS = typename FixStore<T, C12>::W;
+  using GS = typename FixStore<T, C12>::G;
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
   const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
   double r = 0.0;
   if (h < d.g.Vh) {
-    const Links<T> W{d.W, d.g.Vh};
-    const Gauge G{d.G, d.g.Vh};
+    const WS W{d.W, d.g.Vh};
+    const GS G{d.G, d.g.Vh};
     int c[4];
     coords_of(d.g, par, h, c);
     const unsigned of = W.off(par, h);
@@ -98,28 +102,52 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
     }
     M3<T> F[4], Bk[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) F[mu] = W.load_off(mu, of);
+    for (int mu = 0; mu < 4; mu++) {
+      if constexpr (C12) F[mu] = W.load_rows(mu, of);
+      else F[mu] = W.load_off(mu, of);
+    }
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) Bk[mu] = W.load_off(mu, ob[mu]);
+    for (int mu = 0; mu < 4; mu++) {
+      if constexpr (C12) Bk[mu] = W.load_rows(mu, ob[mu]);
+      else Bk[mu] = W.load_off(mu, ob[mu]);
+    }
 
     M3<T> X = m_zero<T>();
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) axpy(conj(trace(F[mu])), F[mu], X);
+    for (int mu = 0; mu < 4; mu++) {
+      M3<T> f = F[mu];
+      if constexpr (C12) third_row(f);
+      axpy(conj(trace(f)), f, X);
+    }
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) axpy_dag(trace(Bk[mu]), Bk[mu], X);
+    for (int mu = 0; mu < 4; mu++) {
+      M3<T> bk = Bk[mu];
+      if constexpr (C12) third_row(bk);
+      axpy_dag(trace(bk), bk, X);
+    }
     const M3<T> g = local_update<T>(X, omega);
 
 #pragma unroll
     for (int mu = 0; mu < 4; mu++) {
-      const M3<T> f = mul(g, F[mu]);
-      W.store_off(mu, of, f);
-      if (WR) r += tr2(f);
+      M3<T> f = F[mu];
+      if constexpr (C12) {
+        opaque_rows(f);
+        third_row(f);
+      }
+      const M3<T> fn = mul(g, f);
+      W.store_off(mu, of, fn);
+      if (WR) r += tr2(fn);
     }
 #pragma unroll
     for (int mu = 0; mu < 4; mu++) {
-      const M3<T> bk = mul_nd(Bk[mu], g);
-      W.store_off(mu, ob[mu], bk);
-      if (WR) r += tr2(bk);
+      M3<T> bk = Bk[mu];
+      if constexpr (C12) {
+        opaque_rows(bk);
+        third_row(bk);
+      }
+      const M3<T> bn = mul_nd(bk, g);
+      W.store_off(mu, ob[mu], bn);
+      if (WR) r += tr2(bn);
     }
     G.store(par, h, mul(m_cvt<double>(g), G.load(par, h)));
   }
@@ -130,16 +158,19 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
 }
 
 // W = U^G (FP64 products, rounded once), with per-block sums of |tr W|^2.
-template <typename T, int BS>
+template <typename T, int BS, bool C12>
 __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ D, int B, int gated) {
+  using WS = typename FixStore<T, C12>::W;
+  using GS = typename FixStore<T, C12>::G;
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
   const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
   double r = 0.0;
   if (h < d.g.Vh) {
-    const Links<T> W{d.W, d.g.Vh}, U{const_cast<V2<T> *>(d.U), d.g.Vh};
-    const Gauge G{d.G, d.g.Vh};
+    const WS W{d.W, d.g.Vh};
+    const Links<T> U{const_cast<V2<T> *>(d.U), d.g.Vh};
+    const GS G{d.G, d.g.Vh};
     for (int par = 0; par < 2; par++) {
       int c[4];
       coords_of(d.g, par, h, c);
@@ -159,14 +190,15 @@ __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ 
   if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
 }
 
-template <typename T, int BS>
+template <typename T, int BS, bool C12>
 __global__ __launch_bounds__(BS) void k_reunit(const LatDesc<T> *__restrict__ D, int B, int gated) {
+  using GS = typename FixStore<T, C12>::G;
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
   const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
   if (h >= d.g.Vh) return;
-  const Gauge G{d.G, d.g.Vh};
+  const GS G{d.G, d.g.Vh};
   for (int par = 0; par < 2; par++) {
     M3<double> m = G.load(par, h);
     reunit(m);
@@ -175,14 +207,15 @@ __global__ __launch_bounds__(BS) void k_reunit(const LatDesc<T> *__restrict__ D,
 }
 
 // (1/V) sum_x |TA X(x)|^2 partials (both parities; X as in the half-sweep)
-template <typename T, int BS>
+template <typename T, int BS, bool C12>
 __global__ __launch_bounds__(BS) void k_theta(const LatDesc<T> *__restrict__ D, int B) {
+  using WS = typename FixStore<T, C12>::W;
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
   double r = 0.0;
   if (h < d.g.Vh) {
-    const Links<T> W{d.W, d.g.Vh};
+    const WS W{d.W, d.g.Vh};
     for (int par = 0; par < 2; par++) {
       int c[4];
       coords_of(d.g, par, h, c);
@@ -205,6 +238,36 @@ __global__ __launch_bounds__(BS) void k_theta(const LatDesc<T> *__restrict__ D, 
   }
   const double s = block_sum<BS>(r);
   if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+}
+
+// Conversion between the full and the two-row forms (to12: full -> rows;
+// otherwise rows -> full with row 2 rebuilt).  Links: one thread per (h, mu,
+// parity); gauge: one thread per (h, parity).
+template <typename T>
+__global__ __launch_bounds__(256) void k_links_form(Geom g, const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
+                                                    int to12) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= g.Vh) return;
+  const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
+  const Links<T> F{to12 ? const_cast<V2<T> *>(src) : dst, g.Vh};
+  const Links12<T> C{to12 ? dst : const_cast<V2<T> *>(src), g.Vh};
+  if (to12)
+    C.store(mu, par, h, F.load(mu, par, h));
+  else
+    F.store(mu, par, h, C.load(mu, par, h));
+}
+
+__global__ __launch_bounds__(256) void k_gauge_form(Geom g, const double2 *__restrict__ src,
+                                                    double2 *__restrict__ dst, int to12) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= g.Vh) return;
+  const int par = blockIdx.y;
+  const Gauge F{to12 ? const_cast<double2 *>(src) : dst, g.Vh};
+  const Gauge12 C{to12 ? dst : const_cast<double2 *>(src), g.Vh};
+  if (to12)
+    C.store(par, h, F.load(par, h));
+  else
+    F.store(par, h, C.load(par, h));
 }
 
 // ------------------------------------------------------ bookkeeping

@@ -225,3 +225,12 @@ def smear_mcg_backward(U, rho, eps, n, G, ckpt_every=2):
     check(lib().mcg_smear_mcg_backward(ctx(), C.byref(fu), rho, eps, n, C.byref(g), ckpt_every, C.byref(fg),
                                        C.byref(loss), C.byref(dr), C.byref(de), None))
     return grad, loss.value, dr.value, de.value
+
+
+def set_two_row(on):
+    check(lib().mcg_set_option(ctx(), 1, 1 if on else 0))
+
+
+def sweeps(W, G, n, omega=1.7):
+    f, g = W.abi(), G.abi()
+    check(lib().mcg_sweeps(ctx(), C.byref(f), C.byref(g), n, omega, None))

@@ -69,14 +69,29 @@ def scenario_halfsweep(L, prec):
 
 def scenario_fix(L, prec):
     U = rounded(field(L, 2005), prec)
-    G, info = E.fix(E.links(U, prec), None, tol=-1.0, max_sweeps=9, reunit_every=4, check_every=3)
     Go, io, to = O.mcg_fix(U, tol=-1.0, max_sweeps=9, reunit_every=4, want_traj=True)
-    check(info["sweeps"] == io["sweeps"] == 9, "sweep count")
-    check((np.abs(info["traj"] - to) / to).max() < TOL[prec], "trajectory")
-    check(abs(info["R"] - io["R"]) <= TOL[prec] * io["R"], "final R")
-    if prec == 0:
-        check(np.abs(E.host_gauge(G) - Go).max() < 1e-11, "final G")
-        check(abs(info["theta"] - io["theta"]) <= 1e-9 * max(io["theta"], 1e-12), "theta")
+    for two_row in (True, False):
+        E.set_two_row(two_row)
+        G, info = E.fix(E.links(U, prec), None, tol=-1.0, max_sweeps=9, reunit_every=4, check_every=3)
+        check(info["sweeps"] == io["sweeps"] == 9, "sweep count")
+        check((np.abs(info["traj"] - to) / to).max() < TOL[prec], f"trajectory two_row={two_row}")
+        check(abs(info["R"] - io["R"]) <= TOL[prec] * io["R"], "final R")
+        if prec == 0:
+            check(np.abs(E.host_gauge(G) - Go).max() < 1e-11, "final G")
+            check(abs(info["theta"] - io["theta"]) <= 1e-9 * max(io["theta"], 1e-12), "theta")
+    E.set_two_row(True)
+    # raw sweeps in both forms agree with the oracle's half-sweeps
+    G0 = S.haar_gauge(L, S.sub_seed(2009))
+    Wo, Gh = U.copy(), G0.copy()
+    for par in (0, 1, 0, 1):
+        Wo, Gh = O.halfsweep(Wo, Gh, par, 1.7)
+    for two_row in (True, False):
+        E.set_two_row(two_row)
+        W, Gd = E.links(U, prec), E.gauge(G0)
+        E.sweeps(W, Gd, 2)
+        check(np.abs(E.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 2e-5), f"sweeps two_row={two_row}")
+        check(np.abs(E.host_gauge(Gd) - Gh).max() < (1e-13 if prec == 0 else 2e-5), "sweeps gauge")
+    E.set_two_row(True)
 
 
 def scenario_project(L, prec):

@@ -95,13 +95,43 @@ def test_halfsweeps(S, O, g, api, L, prec):
     assert np.abs(g.host_gauge(Gd) - Go).max() < (1e-13 if prec == 0 else 2e-5)
 
 
+@pytest.mark.parametrize("two_row", [True, False])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", [(6, 6, 6, 10), (2, 2, 2, 2)])
+def test_sweeps_every_variant_and_form(S, O, g, api, L, prec, two_row):
+    """Raw sweeps at every launch variant, in both storage forms of the
+    working field, against the oracle's half-sweeps."""
+    U = g.rounded(field(S, L, 1010), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1011))
+    Wo, Go = U.copy(), G0.copy()
+    for par in (0, 1, 0, 1, 0, 1):
+        Wo, Go = O.halfsweep(Wo, Go, par, 1.7)
+    api.set_two_row(two_row)
+    try:
+        for v in range(6):
+            api.set_variant(prec, v)
+            W, Gd = g.links(U, prec), g.gauge(G0)
+            api.sweeps(W, Gd, 3)
+            assert np.abs(g.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 3e-5), v
+            assert np.abs(g.host_gauge(Gd) - Go).max() < (1e-13 if prec == 0 else 3e-5), v
+        api.set_variant(prec, 2)
+    finally:
+        api.set_two_row(True)
+
+
+@pytest.mark.parametrize("two_row", [True, False])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("L", LATS)
-def test_fix_trajectory(S, O, g, api, L, prec):
-    """40 sweeps with re-unitarisation every 7: R after every sweep matches."""
+def test_fix_trajectory(S, O, g, api, L, prec, two_row):
+    """40 sweeps with re-unitarisation every 7: R after every sweep matches,
+    with the working field kept as two rows or as full matrices."""
     U = g.rounded(field(S, L, 1008), prec)
-    G, info = api.fix(g.links(U, prec), None, tol=-1.0, max_sweeps=40, reunit_every=7,
-                      check_every=9, want_traj=True)
+    api.set_two_row(two_row)
+    try:
+        G, info = api.fix(g.links(U, prec), None, tol=-1.0, max_sweeps=40, reunit_every=7,
+                          check_every=9, want_traj=True)
+    finally:
+        api.set_two_row(True)
     Go, io, to = O.mcg_fix(U, tol=-1.0, max_sweeps=40, reunit_every=7, want_traj=True)
     assert info["sweeps"] == io["sweeps"] == 40 and info["status"] == io["status"] == 1
     rel = np.abs(info["traj"] - to) / to
