@@ -10,9 +10,12 @@ Workload (one "step" = the whole path over one batch of synthetic fields):
   projection and P-vortex counting of every field.
 Metric: MCG site-updates per second over the timed steps (site-updates =
   sum over fields of sweeps x V), plus the roofline of the half-sweep
-  kernel at 32^3x64 and the FP64 CPU oracle timed on a bounded sample.
+  kernel at 32^3x64, the FP64 CPU oracle timed on a bounded sample, and
+  Gribov copies per second of the 20^3x40 field: 16 Haar copies batched with
+  FP32 links against the same copies fixed one by one with FP64 links, per
+  smearing level, with the copies whose final R agree to 1e-6 counted.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-gribov]
     python bench.py --profile      # short fixed-work run for rocprofv3
 """
 import argparse
@@ -58,6 +61,123 @@ def make_inputs(api, synth, torch):
             f"plaquette {api.plaquette(U):.5f}")
         fields.append((L, U, U64 if i == 0 else None))
     return fields
+
+
+def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-7, max_sweeps=5000,
+                  r_match=1e-6):
+    """Gribov copies of one field: Haar-random start transforms g_c, each copy
+    fixed without smearing and with nsmear stout steps (then carried back and
+    re-fixed), centre-projected and vortex-counted.  Every level runs once with
+    all copies batched in FP32 links and once copy by copy with FP64 links
+    (the same FP32-rounded input); a copy counts as matched when its two final
+    R agree to r_match.  Rounding differences steer a copy to a different
+    local maximum after enough over-relaxed sweeps, so the R distributions of
+    the two precisions are compared too (means, standard errors, Welch t), and
+    the sweep at which each copy's two R trajectories first differ by more
+    than r_match is reported."""
+    import numpy as np
+
+    L = U.L
+    U64 = api.to_links(api.from_links(U).to(torch.complex128), 0)
+    G0 = [api.to_gauge(synth.haar_gauge_gpu(L, synth.sub_seed(7), c)) for c in range(ncopies)]
+    V = api.volume(L)
+    fix_kw = dict(tol=tol, max_sweeps=max_sweeps, omega=1.7, check_every=50)
+
+    def finish(W, G, infos, infos_s):
+        out = []
+        for c in range(ncopies):
+            Z, _ = api.center_project(W, G[c])
+            v = api.count_vortices(Z, L)
+            sw = infos[c]["sweeps"] + (infos_s[c]["sweeps"] if infos_s else 0)
+            first = (infos_s or infos)[c]  # the first fix of the level
+            out.append(dict(R=infos[c]["R"], sweeps=sw, vf=v["total"] / (6 * V), status=infos[c]["status"],
+                            traj=first["traj"][:first["sweeps"] + 1]))
+        return out
+
+    def batched(n):
+        G = [g.clone() for g in G0]
+        infos_s = None
+        if n:
+            S = api.smear(U, rho, 1.0, n)
+            G, infos_s = api.fix_batch([S] * ncopies, G, want_traj=True, **fix_kw)
+            del S
+        G, infos = api.fix_batch([U] * ncopies, G, want_traj=True, **fix_kw)
+        return finish(U, G, infos, infos_s)
+
+    def plain(n):
+        S = api.smear(U64, rho, 1.0, n) if n else None
+        G, infos, infos_s = [], [], [] if n else None
+        for c in range(ncopies):
+            g = G0[c].clone()
+            if n:
+                g, i_s = api.fix(S, g, want_traj=True, **fix_kw)
+                infos_s.append(i_s)
+            g, i = api.fix(U64, g, want_traj=True, **fix_kw)
+            G.append(g)
+            infos.append(i)
+        return finish(U64, G, infos, infos_s)
+
+    def mean_sem(x):
+        x = np.asarray(x, dtype=float)
+        return float(x.mean()), float(x.std(ddof=1) / np.sqrt(len(x)))
+
+    def diverge(ta, tb):
+        n = min(len(ta), len(tb))
+        d = np.nonzero(np.abs(ta[:n] - tb[:n]) > r_match)[0]
+        return int(d[0]) if len(d) else None
+
+    best64, _ = api.autotune(U64)
+    levels = []
+    for n in (0, nsmear):
+        runs = {}
+        for name, fn in (("fp32_batched", batched), ("fp64_plain", plain)):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            runs[name] = fn(n)
+            torch.cuda.synchronize()
+            runs[name + "_s"] = time.time() - t0
+            log(f"gribov copies n={n} {name}: {runs[name + '_s']:.2f} s")
+        a, b = runs["fp32_batched"], runs["fp64_plain"]
+        dR = [abs(x["R"] - y["R"]) for x, y in zip(a, b)]
+        matched = [c for c in range(ncopies) if dR[c] <= r_match]
+        (ma, sa), (mb, sb) = mean_sem([x["R"] for x in a]), mean_sem([x["R"] for x in b])
+        (va, vsa), (vb, vsb) = mean_sem([x["vf"] for x in a]), mean_sem([x["vf"] for x in b])
+        div = [diverge(x["traj"], y["traj"]) for x, y in zip(a, b)]
+        levels.append(dict(
+            smear=f"stout rho={rho} n={n}" if n else "none",
+            copies_per_s_fp32_batched=round(ncopies / runs["fp32_batched_s"], 3),
+            copies_per_s_fp64_plain=round(ncopies / runs["fp64_plain_s"], 3),
+            speedup=round(runs["fp64_plain_s"] / runs["fp32_batched_s"], 3),
+            matched_copies=len(matched), max_abs_dR_matched=max([dR[c] for c in matched], default=None),
+            R_mean_sem_fp32=[round(ma, 7), round(sa, 7)], R_mean_sem_fp64=[round(mb, 7), round(sb, 7)],
+            R_welch_t=round((ma - mb) / np.hypot(sa, sb), 3),
+            vortex_fraction_mean_sem_fp32=[round(va, 6), round(vsa, 6)],
+            vortex_fraction_mean_sem_fp64=[round(vb, 6), round(vsb, 6)],
+            trajectories_differ_by_r_match_at_sweep=div,
+            R_fp32=[round(x["R"], 7) for x in a], R_fp64=[round(x["R"], 7) for x in b],
+            sweeps_fp32=[x["sweeps"] for x in a], sweeps_fp64=[x["sweeps"] for x in b],
+            vortex_fraction_fp32=[round(x["vf"], 5) for x in a],
+            vortex_fraction_fp64=[round(x["vf"], 5) for x in b],
+            not_converged=sum(x["status"] != 0 for x in a + b)))
+    return dict(workload=f"{ncopies} Haar Gribov copies of one {'x'.join(map(str, L))} field, "
+                         f"tol {tol}, all copies batched (FP32 links) vs one by one (FP64 links)",
+                fp64_variant=best64, levels=levels)
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate of the runtime's copy kernel (bytes read +
+    written), the practical ceiling that an HBM-bound kernel is compared with."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    return round(2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
 
 
 def one_step(api, fields, tol=1e-7, max_sweeps=5000):
@@ -161,6 +281,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gribov", action="store_true", help="skip the Gribov-copy comparison")
     ap.add_argument("--profile", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -197,7 +318,9 @@ def main():
     value = total / elapsed
 
     roof = roofline(api, torch, fields[0][1])
+    roof["copy_ceiling_GBps"] = copy_ceiling(torch)
     log(f"roofline: {roof}")
+    gribov = None if args.no_gribov else gribov_copies(api, synth, torch, fields[2][1])
     line = dict(metric=METRIC, value=round(value, 1), unit="site-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(1000 * elapsed / args.steps, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -211,6 +334,8 @@ def main():
                                             vortex_fraction=round(x["vortex_fraction"], 5))
                                        for x in results[-1]]),
                 roofline=roof)
+    if gribov is not None:
+        line["gribov_copies"] = gribov
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(fields[0][2])
     print(json.dumps(line), flush=True)

@@ -90,7 +90,11 @@ def test_c4_finite_differences_fp64(S, env, c4):
         E = (V * np.exp(1j * s * w)[:, None, :]) @ np.conj(np.swapaxes(V, -1, -2))
         return api.to_links(torch.from_numpy((E.reshape(Uh.shape) @ Uh)).cuda(), 0)
 
-    fd = _fd(lambda s: _loss(api, moved(s), rho, eps, n, G), h)
+    # the derivative along a unit tangent spread over all 4V links is O(1/4V);
+    # at h = 1e-4 the stencil's rounding floor (about 1.5 eps L / h) would be a
+    # few 1e-6 of it, so the step is 1e-2 (each link then moves by ~1e-5, where
+    # the h^4 truncation term is negligible)
+    fd = _fd(lambda s: _loss(api, moved(s), rho, eps, n, G), 1e-2)
     an = inner(g.host_links(grad), X @ Uh)
     assert abs(fd - an) <= 1e-6 * abs(an)
 
