@@ -680,6 +680,54 @@ void or_center_project(const int32_t L[4], const ocx *U, const ocx *G,
     }
 }
 
+/* Sec. III.B: a field splits into its projected centre part Z and the rest,
+ * U^G = Z (Z^dagger U^G); the vortex-removed field is Z^dagger U^G. */
+void or_vortex_field(const int32_t L[4], const ocx *U, const ocx *G,
+                     const int8_t *Z, int mode, ocx *out) {
+  lat_t lt = mklat(L);
+  if (mode == 1) {
+    if (G)
+      or_apply_gauge(L, U, G, out);
+    else
+      memcpy(out, U, sizeof(ocx) * 36 * lt.V);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < lt.V; x++)
+    for (int mu = 0; mu < 4; mu++) {
+      ocx z = cexp(2.0 * M_PI * I * Z[4 * x + mu] / 3.0);
+      ocx *o = link_w(out, x, mu);
+      if (mode == 0) {
+        m_ident(o);
+        for (int k = 0; k < 9; k++) o[k] *= z;
+      } else {
+        for (int k = 0; k < 9; k++) o[k] *= conj(z);
+      }
+    }
+}
+
+double or_wilson_path(const int32_t L[4], const ocx *U, const int *spatial,
+                      int n, int t) {
+  lat_t lt = mklat(L);
+  int len = 2 * (n + t);
+  int *st = malloc(len * sizeof(int));
+  int k = 0;
+  for (int q = 0; q < n; q++) st[k++] = spatial[q];
+  for (int q = 0; q < t; q++) st[k++] = 4;
+  for (int q = n - 1; q >= 0; q--) st[k++] = -spatial[q];
+  for (int q = 0; q < t; q++) st[k++] = -4;
+  double *a = malloc(lt.V * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < lt.V; x++) {
+    ocx P[9];
+    walk(&lt, U, x, st, len, P);
+    a[x] = creal(m_tr(P)) / 3.0;
+  }
+  double s = kahan(a, lt.V);
+  free(a);
+  free(st);
+  return s / lt.V;
+}
+
 /* n = (m_mu(x) + m_nu(x+mu) - m_mu(x+nu) - m_nu(x)) mod 3 for mu < nu; the
  * plaquette is a P-vortex when n != 0.  Planes in the order
  * (0,1),(0,2),(0,3),(1,2),(1,3),(2,3). */

@@ -101,6 +101,18 @@ void or_count_vortices(const int32_t L[4], const int8_t *Z, int64_t *total,
                        int64_t per_plane[6], int64_t per_charge[2],
                        int8_t *n_out);
 
+/* ---- vortex-only / vortex-removed fields, Wilson loops (Sec. III.B) ------ */
+/* mode 0: out_mu(x) = z(m_mu(x)) 1 (the projected centre field);
+ * mode 1: out_mu(x) = conj(z(m_mu(x))) U^G_mu(x) (P-vortices removed);
+ * z(m) = exp(2 pi i m / 3); G may be NULL (identity). */
+void or_vortex_field(const int32_t L[4], const ocx *U, const ocx *G,
+                     const int8_t *Z, int mode, ocx *out);
+/* mean over all sites x of Re tr(loop)/3, the loop running along the spatial
+ * steps (+-(axis+1), axis < 3) from x, then t steps up in time, back along the
+ * spatial steps reversed, and t steps down in time */
+double or_wilson_path(const int32_t L[4], const ocx *U, const int *spatial,
+                      int n, int t);
+
 /* ---- smeared-field MCG loss and its FP64 adjoint ------------------------ */
 double or_smear_loss(const int32_t L[4], const ocx *U, double rho, double eps,
                      int n, const ocx *Gstar);

@@ -65,6 +65,8 @@ def _declare(l):
                                  C.c_int32, _P, C.POINTER(FixResult)]),
         "or_center_project": (None, [_I4, _P, _P, _P, _P]),
         "or_count_vortices": (None, [_I4, _P, _P, _P, _P, _P]),
+        "or_vortex_field": (None, [_I4, _P, _P, _P, C.c_int, _P]),
+        "or_wilson_path": (C.c_double, [_I4, _P, _P, C.c_int, C.c_int]),
         "or_smear_loss": (C.c_double, [_I4, _P, C.c_double, C.c_double, C.c_int, _P]),
         "or_smear_loss_grad": (None, [_I4, _P, C.c_double, C.c_double, C.c_int, _P, C.c_int,
                                       _P, _P, _P, _P]),
@@ -264,6 +266,70 @@ def count_vortices(Z, want_n=False):
     if want_n:
         out["n"] = n
     return out
+
+
+# ---- vortex-only / vortex-removed fields and Wilson loops (Sec. III.B) ----------
+VORTEX_ONLY, VORTEX_REMOVED = 0, 1
+
+
+def vortex_field(U, G, Z, mode):
+    """mode VORTEX_ONLY: z(m) 1 per link; VORTEX_REMOVED: conj(z(m)) U^G."""
+    U = _c128(U)
+    out = np.empty_like(U)
+    Gc = _c128(G) if G is not None else None
+    Zc = np.ascontiguousarray(Z, dtype=np.int8)
+    lib().or_vortex_field(_dims(dims_of(U)), _ptr(U), _ptr(Gc), _ptr(Zc), int(mode), _ptr(out))
+    return out
+
+
+def staircase(d):
+    """Unit spatial steps (+-(axis+1)) from x to x + d: at each step the axis
+    with steps left whose (taken + 1/2) / |d_axis| is smallest, ties to the
+    lower axis, so the path stays close to the straight line."""
+    taken = [0, 0, 0]
+    steps = []
+    for _ in range(sum(abs(v) for v in d)):
+        best, key = None, None
+        for a in range(3):
+            if taken[a] < abs(d[a]):
+                k = (taken[a] + 0.5) / abs(d[a])
+                if key is None or k < key:
+                    best, key = a, k
+        taken[best] += 1
+        steps.append((best + 1) if d[best] > 0 else -(best + 1))
+    return steps
+
+
+def path_images(steps):
+    """The distinct images of a spatial step sequence under the 48 axis
+    permutations and reflections of the cubic lattice (an image maps every
+    step +-(a+1) to +-s_a (p_a + 1))."""
+    import itertools
+    out = set()
+    for p in itertools.permutations(range(3)):
+        for sg in itertools.product((1, -1), repeat=3):
+            out.add(tuple((1 if st > 0 else -1) * sg[abs(st) - 1] * (p[abs(st) - 1] + 1) for st in steps))
+    return sorted(out)
+
+
+def wilson_path(U, spatial, t):
+    U = _c128(U)
+    st = np.ascontiguousarray(spatial, dtype=np.int32)
+    return lib().or_wilson_path(_dims(dims_of(U)), _ptr(U), _ptr(st), len(st), int(t))
+
+
+def wilson_loops(U, vecs, rmax, tmax):
+    """W[i, k-1, T-1]: Wilson loops of time extent T whose spatial side is the
+    staircase of v_i repeated k times, averaged over all sites and over the
+    distinct cubic images of that spatial path."""
+    U = _c128(U)
+    W = np.zeros((len(vecs), rmax, tmax))
+    for i, v in enumerate(vecs):
+        imgs = path_images(staircase(v))
+        for k in range(1, rmax + 1):
+            for T in range(1, tmax + 1):
+                W[i, k - 1, T - 1] = sum(wilson_path(U, list(p) * k, T) for p in imgs) / len(imgs)
+    return W
 
 
 # ---- loss and adjoint -----------------------------------------------------------
