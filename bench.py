@@ -164,6 +164,37 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-7
                 fp64_variant=best64, levels=levels)
 
 
+# Wilson loops of the static-potential measurement (Sec. III.B) on the 20^3x40
+# field: on-axis and off-axis spatial directions with R up to about L/2, T <= 10
+LOOP_VECS = [((1, 0, 0), 10), ((1, 1, 0), 7), ((2, 1, 0), 5), ((1, 1, 1), 5), ((2, 1, 1), 5), ((2, 2, 1), 5)]
+LOOP_TMAX = 10
+
+
+def wilson_loop_run(api, torch, U, G=None, reps=3):
+    """W(R, T) of the fixed field, its vortex-only and its vortex-removed
+    parts (the three fields whose potentials the paper compares), timed."""
+    fields = [("original", U)]
+    if G is not None:
+        Z, _ = api.center_project(U, G)
+        fields += [("vortex-only", api.vortex_field(U, G, Z, 0)), ("vortex-removed", api.vortex_field(U, G, Z, 1))]
+    out = {}
+    for name, F in fields:
+        for v, r in LOOP_VECS:
+            api.wilson_loops(F, [v], r, LOOP_TMAX)  # warm-up (scratch allocation)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(reps):
+            W = [api.wilson_loops(F, [v], r, LOOP_TMAX)[0] for v, r in LOOP_VECS]
+        dt = (time.time() - t0) / reps
+        out[name] = dict(ms=round(1000 * dt, 2), W_R1=[round(float(w[0, 0]), 6) for w in W],
+                         W_onaxis_T1=[round(float(x), 6) for x in W[0][:, 0]])
+    n_loops = sum(r for _, r in LOOP_VECS) * LOOP_TMAX
+    return dict(workload=f"W(R, T) for spatial directions {[v for v, _ in LOOP_VECS]} with k = 1..rmax "
+                         f"{[r for _, r in LOOP_VECS]} copies of the staircase path, T = 1..{LOOP_TMAX}, averaged "
+                         f"over sites and cubic images; {n_loops} (R, T) entries per field",
+                fields=out)
+
+
 def copy_ceiling(torch, nbytes=1 << 30, reps=10):
     """Device-to-device copy rate of the runtime's copy kernel (bytes read +
     written), the practical ceiling that an HBM-bound kernel is compared with."""
@@ -283,6 +314,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gribov", action="store_true", help="skip the Gribov-copy comparison")
     ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--profile-loops", action="store_true", help="short Wilson-loop run for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the workload is one MI355X's share of the job, and "
@@ -295,6 +327,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.profile:
         profile_run(api, torch, synth)
+        return
+    if args.profile_loops:
+        L = LATTICES[2]
+        U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(5, 2), 5.7, 50), 1)
+        r = wilson_loop_run(api, torch, U, None, reps=1)
+        print(json.dumps(dict(profile="done", lattice=L, **r)))
         return
 
     fields = make_inputs(api, synth, torch)
@@ -321,6 +359,9 @@ def main():
     roof["copy_ceiling_GBps"] = copy_ceiling(torch)
     log(f"roofline: {roof}")
     gribov = None if args.no_gribov else gribov_copies(api, synth, torch, fields[2][1])
+    G20, _ = api.fix(fields[2][1], None, tol=1e-7, max_sweeps=5000)
+    loops = wilson_loop_run(api, torch, fields[2][1], G20)
+    log(f"wilson loops: {loops['fields']}")
     line = dict(metric=METRIC, value=round(value, 1), unit="site-updates/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(1000 * elapsed / args.steps, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -336,6 +377,7 @@ def main():
                 roofline=roof)
     if gribov is not None:
         line["gribov_copies"] = gribov
+    line["wilson_loops"] = loops
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(fields[0][2])
     print(json.dumps(line), flush=True)

@@ -231,6 +231,30 @@ mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge 
 mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t *total,
                               int64_t *per_plane, int64_t *per_charge, void *stream);
 
+/* ---- vortex-only and vortex-removed fields, Wilson loops (Sec. III.B) ------------- */
+/* The projected centre field splits a fixed field as U^G = Z (Z^dagger U^G).
+ * mode MCG_VORTEX_ONLY:    out_mu(x) = z(m_mu(x)) 1
+ * mode MCG_VORTEX_REMOVED: out_mu(x) = conj(z(m_mu(x))) G(x) U_mu(x) G(x+mu)^dagger
+ * with z(m) = exp(2 pi i m / 3), Z as written by mcg_center_project (device,
+ * [4][V]), G nullable (identity).  out has U's extents and precision, may
+ * alias U, and is written in U's layout (products formed in FP64). */
+#define MCG_VORTEX_ONLY 0
+#define MCG_VORTEX_REMOVED 1
+mcg_status mcg_vortex_field(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, const int8_t *Z,
+                            int32_t mode, mcg_field *out, void *stream);
+/* Wilson loops W[i][k-1][T-1] (host, nvec * rmax * tmax doubles): the mean
+ * over all sites of Re tr(loop)/3 for time extent T = 1..tmax and the
+ * spatial side made of k = 1..rmax copies of a staircase path for the
+ * integer vector vec[3 i .. 3 i + 2] (host), averaged over the distinct
+ * images of that path under the 48 axis permutations and reflections.
+ * The staircase takes |v_0| + |v_1| + |v_2| unit steps; each step goes
+ * along the axis with steps left whose (steps taken + 1/2) / |v_axis| is
+ * smallest, the lower axis on a tie.  Requires 1 <= tmax <= L[3],
+ * 0 < |v|_1 <= 24 with |v_j| <= 8, and rmax * max_j |v_j| <= min(L[0], L[1],
+ * L[2]); sums in FP64, deterministic.  Synchronises the stream. */
+mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, const int32_t *vec,
+                            int32_t rmax, int32_t tmax, double *W, void *stream);
+
 /* ---- gradient of the smeared-field functional ---------------------------------- */
 /* L = R(S_n(U; rho, eps)^{G*}) at fixed G* (at a converged maximum this is
  * dL/dtheta of the fixed functional by the envelope theorem).  Returns the

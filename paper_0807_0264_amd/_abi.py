@@ -13,6 +13,7 @@ MCG_OK, MCG_WNOTCONV, MCG_EINVAL, MCG_ENOMEM, MCG_EHIP, MCG_EINPUT = 0, 1, -1, -
 MCG_F64, MCG_F32 = 0, 1
 MCG_NUM_VARIANTS = 6
 MCG_OPT_TWO_ROW = 1
+MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 
 class Dims(C.Structure):
@@ -73,6 +74,9 @@ SIGNATURES = {
                                 C.POINTER(C.c_double), _P]),
     "mcg_count_vortices": (_S, [_CTX, _P, Dims, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int64), _P]),
+    "mcg_vortex_field": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P, C.c_int32, C.POINTER(Field), _P]),
+    "mcg_wilson_loops": (_S, [_CTX, C.POINTER(Field), C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                              C.POINTER(C.c_double), _P]),
     "mcg_smear_mcg_backward": (_S, [_CTX, C.POINTER(Field), C.c_double, C.c_double, C.c_int32,
                                     C.POINTER(Gauge), C.c_int32, C.POINTER(Field),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),

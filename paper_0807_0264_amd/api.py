@@ -331,6 +331,35 @@ def count_vortices(Z, L):
     return dict(total=tot.value, per_plane=list(pp), per_charge=list(pc))
 
 
+def vortex_field(U, G, Z, mode, out=None):
+    """Vortex-only field (mode A.MCG_VORTEX_ONLY: z(m) 1 on every link) or
+    vortex-removed field (A.MCG_VORTEX_REMOVED: conj(z(m)) U^G), with Z from
+    center_project(U, G) (Sec. III.B).  out may be U itself."""
+    out = out if out is not None else empty_links(U.L, U.prec, U.data.device.index)
+    ctx = context(U.data.device.index)
+    fu, fo = U.abi(), out.abi()
+    g = G.abi() if G is not None else None
+    if Z.dtype != torch.int8 or Z.numel() != 4 * volume(U.L) or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous int8 tensor of 4 V entries")
+    _check(A.load().mcg_vortex_field(ctx, C.byref(fu), C.byref(g) if g is not None else None,
+                                     C.c_void_p(Z.data_ptr()), int(mode), C.byref(fo), _stream()), ctx)
+    return out
+
+
+def wilson_loops(U, vecs, rmax, tmax):
+    """W[i, k-1, T-1] (numpy): Wilson loops of time extent T whose spatial side
+    is k copies of the staircase path of vecs[i], averaged over all sites and
+    the cubic images of the path."""
+    import numpy as np
+    v = np.ascontiguousarray(np.asarray(vecs, dtype=np.int32).reshape(-1, 3))
+    W = np.zeros((len(v), int(rmax), int(tmax)))
+    ctx = context(U.data.device.index)
+    f = U.abi()
+    _check(A.load().mcg_wilson_loops(ctx, C.byref(f), len(v), v.ctypes.data_as(C.POINTER(C.c_int32)), int(rmax),
+                                     int(tmax), W.ctypes.data_as(C.POINTER(C.c_double)), _stream()), ctx)
+    return W
+
+
 def smear_mcg_backward(U, rho, eps, n, Gstar, ckpt_every=5):
     """Gradient of L = R(S_n(U; rho, eps)^{G*}) at fixed G*: returns
     (gradU Links (ambient), L, dL/drho, dL/deps)."""

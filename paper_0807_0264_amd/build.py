@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_mcg.hip", "k_field.hip", "k_smear.hip", "k_project.hip", "k_backward.hip", "mcg_api.cpp"]
+SOURCES = ["k_mcg.hip", "k_field.hip", "k_smear.hip", "k_project.hip", "k_backward.hip", "k_loops.hip",
+           "mcg_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,

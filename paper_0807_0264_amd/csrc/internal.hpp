@@ -61,6 +61,28 @@ hipError_t launch_center_project(const Geom &g, const void *U, const double *G, 
 hipError_t launch_count_vortices(const Geom &g, const int8_t *Z, unsigned long long *counts,
                                  hipStream_t s);
 
+// k_loops.hip -- vortex-only / vortex-removed fields and Wilson loops.
+// A spatial path for the line kernel: n unit steps +-(axis+1), displacement d.
+struct SPathArg {
+  int n;
+  int d[3];
+  int s[32];
+};
+template <typename T>
+hipError_t launch_vortex_field(const Geom &g, const void *U, const double *G, const int8_t *Z, int mode, void *out,
+                               hipStream_t s);
+int line_blocks(const Geom &g);
+// out(x) = in(x) * path product from x + off (in null: 1); line fields hold 9 V complex of T
+template <typename T>
+hipError_t launch_line(const Geom &g, const void *U, const void *in, const SPathArg &path, const int off[3],
+                       void *out, hipStream_t s);
+// res[t] += weight * sum_x Re tr(loop with spatial line S, displacement D, time extent t + 1),
+// t < tmax; part holds tmax * line_blocks(g) doubles
+template <typename T>
+hipError_t launch_wloop(const Geom &g, const void *U, const void *S, const int D[3], int tmax, double *part,
+                        double weight, double *res, hipStream_t s);
+hipError_t launch_zero(double *p, int n, hipStream_t s);
+
 // k_backward.hip -- adjoint of one smearing step and the loss seed.
 // Seed: per-block sums of |tr W|^2 into part (field_blocks256 entries).
 // Step: per-block (dL/drho, dL/deps) pairs into part[0 .. 2 nb) and, for

@@ -1,0 +1,169 @@
+// loops_kernels.hpp -- vortex-only / vortex-removed fields and Wilson loops
+// (launchers in k_loops.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace mcg {
+
+// site coordinates c moved by the spatial offset (o0, o1, o2) and dt in time,
+// each |offset| < 2 L (periodic)
+__device__ __forceinline__ void shifted(const Geom &g, const int c[4], int o0, int o1, int o2, int dt,
+                                        int e[4]) {
+  const int o[4] = {o0, o1, o2, dt};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    int v = c[k] + o[k];
+    v = v < 0 ? v + g.L[k] : v;
+    v = v < 0 ? v + g.L[k] : v;
+    v = v >= g.L[k] ? v - g.L[k] : v;
+    v = v >= g.L[k] ? v - g.L[k] : v;
+    e[k] = v;
+  }
+}
+
+// z(m) = exp(2 pi i m / 3) for m in {-1, 0, 1}
+__device__ __forceinline__ cx<double> center_elem(int m) {
+  const double s3 = 0.86602540378443864676;  // sqrt(3)/2
+  return m == 0 ? cx<double>{1.0, 0.0} : cx<double>{-0.5, m > 0 ? s3 : -s3};
+}
+
+// mode 0: out_mu(x) = z(m_mu(x)) 1; mode 1: out_mu(x) = conj(z(m_mu(x))) G(x) U_mu(x) G(x+mu)^dag
+// (G may be null: identity).  One thread per half index h, both parities.  out may alias U: every
+// element is read and written by the same thread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vortex_field(Geom g, const V2<T> *U, const double2 *__restrict__ G,
+                                                      const int8_t *__restrict__ Z, int mode, V2<T> *out) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= g.Vh) return;
+  const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+  const Links<T> O{out, g.Vh};
+  const Gauge gg{const_cast<double2 *>(G), g.Vh};
+  for (int par = 0; par < 2; par++) {
+    int c[4];
+    coords_of(g, par, h, c);
+    const int i = lex_index(g, c);
+    M3<double> Gx;
+    if (mode == 1 && G) Gx = gg.load(par, h);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+      const cx<double> z = center_elem(Z[(size_t)mu * g.V + i]);
+      M3<double> r;
+      if (mode == 0) {
+        r = m_zero<double>();
+        r.e[0] = r.e[4] = r.e[8] = z;
+      } else {
+        const M3<double> u = m_cvt<double>(L.load(mu, par, h));
+        if (G) {
+          int e[4];
+          moved(g, c, mu, +1, e);
+          r = mul_nd(mul(Gx, u), gg.load(1 - par, half_index(g, e)));
+        } else {
+          r = u;
+        }
+        const cx<double> zc = conj(z);
+#pragma unroll
+        for (int k = 0; k < 9; k++) r.e[k] = r.e[k] * zc;
+      }
+      O.store(mu, par, h, m_cvt<T>(r));
+    }
+  }
+}
+
+constexpr int MAX_PATH = 32;
+// a spatial step sequence: steps +-(axis + 1), axis < 3
+struct SPath {
+  int n;
+  int d[3];  // displacement of the whole path
+  signed char s[MAX_PATH];
+};
+
+// out(x) = in(x) * (product of the links along `path` starting at x + off), in = null meaning 1.
+// Line fields use the link layout with a single direction.  Grid: 2 * ceil(Vh / 256) blocks,
+// the first half even sites, the second half odd sites.
+template <typename T>
+__global__ __launch_bounds__(256) void k_line(Geom g, const V2<T> *__restrict__ U, const V2<T> *in, SPath path,
+                                              int o0, int o1, int o2, V2<T> *out) {
+  const int nbp = gridDim.x >> 1;
+  const int par = blockIdx.x >= nbp;
+  const int h = (blockIdx.x - par * nbp) * 256 + threadIdx.x;
+  if (h >= g.Vh) return;
+  const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+  int c[4];
+  coords_of(g, par, h, c);
+  M3<T> M = in ? Links<T>{const_cast<V2<T> *>(in), g.Vh}.load(0, par, h) : m_ident<T>();
+  int y[4];
+  shifted(g, c, o0, o1, o2, 0, y);
+  for (int q = 0; q < path.n; q++) {
+    const int st = path.s[q];
+    const int a = (st > 0 ? st : -st) - 1;
+    if (st > 0) {
+      M = mul(M, L.at(g, y, a));
+      int e[4];
+      moved(g, y, a, +1, e);
+#pragma unroll
+      for (int k = 0; k < 4; k++) y[k] = e[k];
+    } else {
+      int e[4];
+      moved(g, y, a, -1, e);
+#pragma unroll
+      for (int k = 0; k < 4; k++) y[k] = e[k];
+      M = mul_nd(M, L.at(g, y, a));
+    }
+  }
+  Links<T>{out, g.Vh}.store(0, par, h, M);
+}
+
+// For every site x: the loops with spatial side S(x) (a line field from x to x + D) and time
+// extents T = 1..tmax,  Re tr[ S(x) B_T(x+D) S(x+T)^dag A_T(x)^dag ],  A_T(y) = U_3(y) ... U_3(y+(T-1)),
+// summed per block into part[(T-1) * gridDim.x + blockIdx.x].  Each lane carries P = S(x) B_T(x+D)
+// and A_T(x), one product each per T, and forms Q = A_T(x) S(x+T): Re tr(P Q^dag).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ U, const V2<T> *__restrict__ S,
+                                              int D0, int D1, int D2, int tmax, double *__restrict__ part) {
+  const int nbp = gridDim.x >> 1;
+  const int par = blockIdx.x >= nbp;
+  const int h = (blockIdx.x - par * nbp) * BS + threadIdx.x;
+  const bool live = h < g.Vh;
+  const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+  const Links<T> Sf{const_cast<V2<T> *>(S), g.Vh};
+  int c[4] = {0, 0, 0, 0}, cd[4] = {0, 0, 0, 0};
+  M3<T> P, A;
+  if (live) {
+    coords_of(g, par, h, c);
+    shifted(g, c, D0, D1, D2, 0, cd);
+    P = Sf.load(0, par, h);
+    A = m_ident<T>();
+  }
+  for (int t = 1; t <= tmax; t++) {
+    double val = 0.0;
+    if (live) {
+      int e[4];
+      shifted(g, c, 0, 0, 0, t - 1, e);
+      A = mul(A, L.at(g, e, 3));
+      shifted(g, cd, 0, 0, 0, t - 1, e);
+      P = mul(P, L.at(g, e, 3));
+      shifted(g, c, 0, 0, 0, t, e);
+      const M3<T> Q = mul(A, Sf.load(0, parity_of(e), half_index(g, e)));
+#pragma unroll
+      for (int k = 0; k < 9; k++)
+        val += (double)P.e[k].re * (double)Q.e[k].re + (double)P.e[k].im * (double)Q.e[k].im;
+    }
+    const double s = block_sum<BS>(val);
+    if (threadIdx.x == 0) part[(size_t)(t - 1) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// res[t] += weight * sum_b part[t * nb + b] (fixed order); one block per t
+__global__ __launch_bounds__(256) void k_wloop_final(const double *__restrict__ part, int nb, double weight,
+                                                     double *res) {
+  const double s = sum_partials<256>(part + (size_t)blockIdx.x * nb, nb);
+  if (threadIdx.x == 0) res[blockIdx.x] += weight * s;
+}
+
+__global__ __launch_bounds__(256) void k_zero(double *p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace mcg

@@ -33,6 +33,7 @@ struct mcg_ctx {
   std::string err;
   hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
   DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part, w12, g12;
+  DevBuf line_a, line_b, wl_part, wl_res;  // Wilson loops: line fields, partial sums, results
   std::vector<DevBuf> W, G12, fpart, traj;
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
@@ -472,7 +473,8 @@ mcg_status mcg_destroy(mcg_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   DevBuf *bufs[] = {&ctx->part, &ctx->scalars, &ctx->counts, &ctx->states, &ctx->desc, &ctx->tmpfield,
-                    &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part, &ctx->w12, &ctx->g12};
+                    &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part, &ctx->w12, &ctx->g12,
+                    &ctx->line_a, &ctx->line_b, &ctx->wl_part, &ctx->wl_res};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj})
@@ -921,6 +923,160 @@ mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t
   }
   *total = tot;
   return MCG_OK;
+}
+
+mcg_status mcg_vortex_field(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, const int8_t *Z, int32_t mode,
+                            mcg_field *out, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, out, "out"))) return st;
+  if (G && (st = check_gauge(ctx, G, U->d, "G"))) return st;
+  if (!same_dims(U->d, out->d) || U->prec != out->prec)
+    return fail(ctx, MCG_EINVAL, "U and out differ in extents or precision");
+  if (!Z) return fail(ctx, MCG_EINVAL, "Z is NULL");
+  if (mode != MCG_VORTEX_ONLY && mode != MCG_VORTEX_REMOVED) return fail(ctx, MCG_EINVAL, "bad mode %d", mode);
+  const Geom g = geom_of(U->d);
+  const double *gp = G ? G->ptr : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  if (U->prec == MCG_F64)
+    HIPCHK(launch_vortex_field<double>(g, U->ptr, gp, Z, mode, out->ptr, s));
+  else
+    HIPCHK(launch_vortex_field<float>(g, U->ptr, gp, Z, mode, out->ptr, s));
+  return MCG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// unit steps +-(axis+1) of the staircase from 0 to v: each step along the axis with steps left
+// whose (taken + 1/2) / |v_axis| is smallest, the lower axis on a tie (compared exactly as
+// (2 taken_a + 1) |v_b| < (2 taken_b + 1) |v_a|)
+std::vector<int> staircase_steps(const int v[3]) {
+  int taken[3] = {0, 0, 0}, n = std::abs(v[0]) + std::abs(v[1]) + std::abs(v[2]);
+  std::vector<int> st;
+  for (int q = 0; q < n; q++) {
+    int best = -1;
+    for (int a = 0; a < 3; a++) {
+      if (taken[a] >= std::abs(v[a])) continue;
+      if (best < 0 || (int64_t)(2 * taken[a] + 1) * std::abs(v[best]) <
+                          (int64_t)(2 * taken[best] + 1) * std::abs(v[a]))
+        best = a;
+    }
+    taken[best]++;
+    st.push_back(v[best] > 0 ? best + 1 : -(best + 1));
+  }
+  return st;
+}
+
+// distinct images of a step sequence under the 48 signed axis permutations, each with the
+// number of images it stands for: an image whose reversed, negated sequence (the same loop
+// traversed from its other corner, equal in translation-averaged Re tr) is already listed is
+// merged into that entry
+std::vector<std::pair<std::vector<int>, int>> path_images(const std::vector<int> &base) {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  std::vector<std::vector<int>> all;
+  for (const auto &p : perms)
+    for (int sg = 0; sg < 8; sg++) {
+      std::vector<int> img;
+      for (int st : base) {
+        const int a = std::abs(st) - 1, sign = (st > 0 ? 1 : -1) * ((sg >> a) & 1 ? -1 : 1);
+        img.push_back(sign * (p[a] + 1));
+      }
+      all.push_back(img);
+    }
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  std::vector<std::pair<std::vector<int>, int>> out;
+  for (const auto &img : all) {
+    std::vector<int> rn(img.rbegin(), img.rend());
+    for (int &x : rn) x = -x;
+    bool merged = false;
+    for (auto &e : out)
+      if (e.first == rn) {
+        e.second++;
+        merged = true;
+        break;
+      }
+    if (!merged) out.push_back({img, 1});
+  }
+  return out;
+}
+
+template <typename T>
+mcg_status wilson_impl(mcg_ctx *ctx, const mcg_field *U, int nvec, const int32_t *vec, int rmax, int tmax,
+                       double *W, hipStream_t s) {
+  const Geom g = geom_of(U->d);
+  const size_t line_bytes = (size_t)g.V * 9 * 2 * sizeof(T);
+  const int nres = nvec * rmax * tmax;
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->line_a, line_bytes)) || (st = ensure(ctx, ctx->line_b, line_bytes)) ||
+      (st = ensure(ctx, ctx->wl_part, sizeof(double) * (size_t)tmax * line_blocks(g))) ||
+      (st = ensure(ctx, ctx->wl_res, sizeof(double) * (size_t)nres)))
+    return st;
+  double *res = (double *)ctx->wl_res.p;
+  HIPCHK(launch_zero(res, nres, s));
+  for (int i = 0; i < nvec; i++) {
+    const int v[3] = {vec[3 * i], vec[3 * i + 1], vec[3 * i + 2]};
+    const auto imgs = path_images(staircase_steps(v));
+    int nimg = 0;
+    for (const auto &e : imgs) nimg += e.second;
+    for (const auto &e : imgs) {
+      SPathArg p;
+      p.n = (int)e.first.size();
+      p.d[0] = p.d[1] = p.d[2] = 0;
+      for (int q = 0; q < p.n; q++) {
+        p.s[q] = e.first[q];
+        p.d[std::abs(p.s[q]) - 1] += p.s[q] > 0 ? 1 : -1;
+      }
+      // Re tr / 3, averaged over sites and images
+      const double weight = (double)e.second / (3.0 * (double)nimg * (double)g.V);
+      const void *prev = nullptr;
+      for (int k = 1; k <= rmax; k++) {
+        void *cur = (k & 1) ? ctx->line_a.p : ctx->line_b.p;
+        const int off[3] = {(k - 1) * p.d[0], (k - 1) * p.d[1], (k - 1) * p.d[2]};
+        const int D[3] = {k * p.d[0], k * p.d[1], k * p.d[2]};
+        HIPCHK(launch_line<T>(g, U->ptr, prev, p, off, cur, s));
+        HIPCHK(launch_wloop<T>(g, U->ptr, cur, D, tmax, (double *)ctx->wl_part.p, weight,
+                               res + (size_t)(i * rmax + k - 1) * tmax, s));
+        prev = cur;
+      }
+    }
+  }
+  HIPCHK(hipMemcpyAsync(W, res, sizeof(double) * nres, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return MCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, const int32_t *vec, int32_t rmax,
+                            int32_t tmax, double *W, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U"))) return st;
+  if (nvec < 1 || !vec || !W) return fail(ctx, MCG_EINVAL, "need nvec >= 1, vec and W");
+  if (rmax < 1 || tmax < 1) return fail(ctx, MCG_EINVAL, "rmax and tmax must be >= 1");
+  if (tmax > U->d.L[3]) return fail(ctx, MCG_EINVAL, "tmax %d exceeds L[3] = %d", tmax, U->d.L[3]);
+  const int lmin = std::min(U->d.L[0], std::min(U->d.L[1], U->d.L[2]));
+  if ((int64_t)nvec * rmax * tmax > (int64_t(1) << 24)) return fail(ctx, MCG_EINVAL, "too many loops requested");
+  for (int i = 0; i < nvec; i++) {
+    int n1 = 0, mx = 0;
+    for (int j = 0; j < 3; j++) {
+      const int a = std::abs(vec[3 * i + j]);
+      if (a > 8) return fail(ctx, MCG_EINVAL, "vector %d: components must lie in [-8, 8]", i);
+      n1 += a;
+      mx = std::max(mx, a);
+    }
+    if (n1 == 0 || n1 > 24) return fail(ctx, MCG_EINVAL, "vector %d: need 0 < |v|_1 <= 24", i);
+    if ((int64_t)rmax * mx > lmin)
+      return fail(ctx, MCG_EINVAL, "vector %d: rmax * max|v_j| = %lld exceeds the smallest spatial extent %d", i,
+                  (long long)rmax * mx, lmin);
+  }
+  return U->prec == MCG_F64 ? wilson_impl<double>(ctx, U, nvec, vec, rmax, tmax, W, (hipStream_t)stream)
+                            : wilson_impl<float>(ctx, U, nvec, vec, rmax, tmax, W, (hipStream_t)stream);
 }
 
 mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int32_t n,

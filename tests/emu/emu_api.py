@@ -234,3 +234,21 @@ def set_two_row(on):
 def sweeps(W, G, n, omega=1.7):
     f, g = W.abi(), G.abi()
     check(lib().mcg_sweeps(ctx(), C.byref(f), C.byref(g), n, omega, None))
+
+
+def vortex_field(U, G, Z, mode):
+    out = Links(U.L, U.prec)
+    f, fo = U.abi(), out.abi()
+    g = G.abi() if G is not None else None
+    check(lib().mcg_vortex_field(ctx(), C.byref(f), C.byref(g) if g is not None else None,
+                                 ptr(np.ascontiguousarray(Z, dtype=np.int8)), mode, C.byref(fo), None))
+    return out
+
+
+def wilson_loops(U, vecs, rmax, tmax):
+    v = np.ascontiguousarray(np.asarray(vecs, dtype=np.int32).reshape(-1, 3))
+    W = np.zeros((len(v), rmax, tmax))
+    f = U.abi()
+    check(lib().mcg_wilson_loops(ctx(), C.byref(f), len(v), v.ctypes.data_as(C.POINTER(C.c_int32)), rmax, tmax,
+                                 W.ctypes.data_as(C.POINTER(C.c_double)), None))
+    return W

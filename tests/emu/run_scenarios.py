@@ -152,15 +152,43 @@ def scenario_backward(L, prec):
         check(abs(de - deo) < tol * max(abs(deo), 1e-3) * 10, f"dEps {de} {deo}")
 
 
+def scenario_loops(L, prec):
+    U = rounded(field(L, 2050), prec)
+    G = S.haar_gauge(L, S.sub_seed(2051))
+    Zd, _ = E.center_project(E.links(U, prec), E.gauge(G))
+    Z = E.z_interchange(Zd, L)
+    tol = 1e-14 if prec == 0 else 1e-6
+    for mode in (0, 1):
+        got = E.host_links(E.vortex_field(E.links(U, prec), E.gauge(G), Zd, mode))
+        want = O.vortex_field(U, G, Z, mode)
+        check(np.abs(got - want).max() < tol, f"vortex field mode {mode}")
+    got = E.host_links(E.vortex_field(E.links(U, prec), None, Zd, 1))
+    check(np.abs(got - O.vortex_field(U, None, Z, 1)).max() < tol, "vortex removal without G")
+    # every lane is a host thread here: a few loop shapes only (the GPU tests take many more)
+    cases = ([(1, 0, 0)], 2), ([(2, 1, 0)], 1)
+    if L == (2, 2, 2, 2):
+        cases += (([(1, 1, 1)], 1),)
+    for vecs, rmax in cases:
+        tmax = min(L[3], 3)
+        got = E.wilson_loops(E.links(U, prec), vecs, rmax, tmax)
+        want = O.wilson_loops(U, vecs, rmax, tmax)
+        check(np.abs(got - want).max() < (1e-13 if prec == 0 else 2e-6), f"wilson loops {vecs}")
+
+
 def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
-    names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward"]
+    names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward",
+                             "loops"]
     for name in names:
         if name == "batch":
             for prec in (0, 1):
                 scenario_batch(prec)
         elif name == "planted":
             scenario_planted()
+        elif name == "loops":
+            for L in ((4, 4, 4, 4), (2, 2, 2, 2)):
+                for prec in (0, 1):
+                    scenario_loops(L, prec)
         elif name == "backward":
             for L in ((4, 4, 4, 4), (2, 2, 2, 2)):
                 for prec in (0, 1):
