@@ -315,6 +315,7 @@ def main():
     ap.add_argument("--no-gribov", action="store_true", help="skip the Gribov-copy comparison")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--profile-loops", action="store_true", help="short Wilson-loop run for rocprofv3")
+    ap.add_argument("--profile-step", action="store_true", help="one benchmark step for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the workload is one MI355X's share of the job, and "
@@ -327,6 +328,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.profile:
         profile_run(api, torch, synth)
+        return
+    if args.profile_step:
+        fields = make_inputs(api, synth, torch)
+        api.autotune(fields[0][1])
+        r = one_step(api, fields)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(profile="done", sweeps=[(x["sweeps_smeared"], x["sweeps"]) for x in r])))
         return
     if args.profile_loops:
         L = LATTICES[2]

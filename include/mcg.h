@@ -215,6 +215,15 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * 2/3 of the bytes per site-update; 0 keeps all three rows.  Caller-visible
  * fields and transforms always use the full layouts above. */
 #define MCG_OPT_TWO_ROW 1
+/* MCG_OPT_SLABS (1..16, default 1): the sweeps of mcg_fix, mcg_fix_batch and
+ * mcg_sweeps run each half-sweep of a field in this many slabs of
+ * consecutive time slices (a field too small for slabs of two slices or
+ * more stays whole), ordered even slabs 0, 1, then (even k, odd k-1) for
+ * k = 2..n-1, then odd n-1, odd 0.  Every odd slab runs after the even slabs
+ * it touches and no even slab after an odd slab it touches, so results are
+ * bit-identical to whole half-sweeps; the gain is that a slab's links are
+ * re-read while they may still sit in the device's last-level cache. */
+#define MCG_OPT_SLABS 2
 mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value);
 mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value);
 

@@ -13,6 +13,7 @@ MCG_OK, MCG_WNOTCONV, MCG_EINVAL, MCG_ENOMEM, MCG_EHIP, MCG_EINPUT = 0, 1, -1, -
 MCG_F64, MCG_F32 = 0, 1
 MCG_NUM_VARIANTS = 6
 MCG_OPT_TWO_ROW = 1
+MCG_OPT_SLABS = 2
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 

@@ -394,6 +394,21 @@ def set_two_row(on=True, device=None):
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_TWO_ROW, 1 if on else 0), ctx)
 
 
+def set_slabs(n, device=None):
+    """Run every half-sweep of the fixing loop in n slabs of time slices,
+    pipelined so that a slab is re-read soon after it was written (results
+    are bit-identical for every n)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SLABS, int(n)), ctx)
+
+
+def get_slabs(device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_SLABS, C.byref(v)), ctx)
+    return v.value
+
+
 def get_two_row(device=None):
     ctx = context(device)
     v = C.c_int32()

@@ -25,11 +25,19 @@ struct FixState {
   int32_t pad0, pad1;
 };
 
+constexpr int MAX_SLABS = 16;
+
 // One field in a launch.  Blocks [blk0, blk0 + nblk) of a batched grid work
-// on this field; block j covers half indices [j*BS, (j+1)*BS).
+// on this field; block j covers half indices [j*BS, (j+1)*BS).  A half-sweep
+// may instead run slab by slab: the field's blocks split into nslab
+// contiguous chunks, chunk s = [s*nblk/nslab, (s+1)*nblk/nslab) (all blocks
+// in chunk 0 when nslab = 1), and the launch for slab s maps its grid blocks
+// [sblk0[s], sblk0[s] + size of chunk s) onto that chunk.
 template <typename T> struct LatDesc {
   Geom g;
   int blk0, nblk;
+  int nslab;
+  int sblk0[MAX_SLABS];
   V2<T> *W;        // working field U^G (updated in place)
   const V2<T> *U;  // the field being fixed (read only)
   double2 *G;      // gauge transform (FP64)

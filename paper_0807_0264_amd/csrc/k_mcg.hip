@@ -26,11 +26,11 @@ namespace mcg {
 // c12: working field and transform stored as two rows
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s) {
+                            bool withR, bool gated, hipStream_t s, int slab) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
 #define MCG_HS(WR, OCC, C)                                                                         \
-  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g)))
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab)))
   if (c12) {
     if (variant / 3 == 0) {
       if (withR) { MCG_HS(true, 1, true); } else { MCG_HS(false, 1, true); }
@@ -101,7 +101,7 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t);                                              \
+                                          hipStream_t, int);                                         \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
   template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \

@@ -38,6 +38,7 @@ struct mcg_ctx {
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
+  int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
 };
 
@@ -152,6 +153,34 @@ size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
 }
 
 // ------------------------------------------------------------ fixing driver
+// Slab plan of a launch table: a field is split into n chunks of its blocks (LatDesc) when every
+// chunk holds at least two time slices' worth of half sites.  Every neighbour of a site then lies
+// in the same chunk or the next one on either side (cyclically): spatial neighbours differ by less
+// than one slice in the half index, time neighbours by exactly one slice.  grid[s] = blocks of the
+// launch for slab s.  Returns n, or 1 when no field is split (whole-field launches).
+template <typename T> int plan_slabs(LatDesc<T> *D, int B, int n, int bs, int grid[MAX_SLABS]) {
+  n = std::max(1, std::min(n, MAX_SLABS));
+  bool any = false;
+  for (int b = 0; b < B; b++) {
+    const int64_t vs = (int64_t)D[b].g.L[0] * D[b].g.L[1] * D[b].g.L[2];
+    const bool split = n > 1 && ((int64_t)(D[b].nblk / n) - 1) * bs >= vs;
+    D[b].nslab = split ? n : 1;
+    any = any || split;
+  }
+  for (int k = 0; k < MAX_SLABS; k++) grid[k] = 0;
+  if (!any) return 1;
+  for (int k = 0; k < n; k++) {
+    int tot = 0;
+    for (int b = 0; b < B; b++) {
+      D[b].sblk0[k] = tot;
+      const int nb = D[b].nblk, ns = D[b].nslab;
+      tot += ns > 1 ? ((k + 1) * nb) / ns - (k * nb) / ns : (k == 0 ? nb : 0);
+    }
+    grid[k] = tot;
+  }
+  return n;
+}
+
 template <typename T> struct FixRun {
   mcg_ctx *ctx;
   hipStream_t s;
@@ -159,15 +188,39 @@ template <typename T> struct FixRun {
   bool c12;
   void *dD;  // device LatDesc table
   double omega;
+  int nslab = 1;
+  int grid[MAX_SLABS] = {};
+  bool gated = true;
 
+  mcg_status pass(int par, bool wr, int slab) {
+    const int blocks = slab < 0 ? total_blocks : grid[slab];
+    if (blocks > 0) HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab));
+    return MCG_OK;
+  }
+  // Even then odd half-sweep.  Slab by slab (n > 1), in the order E0 E1 [E(k) O(k-1)] for
+  // k = 2..n-1, O(n-1) O0: odd slab k runs once even slabs k-1, k, k+1 are done, and no even slab
+  // runs after an odd slab next to it, so the result is that of the two whole half-sweeps, while
+  // the data of a slab is re-read soon after it was written.
+  mcg_status halfsweeps(bool wr) {
+    mcg_status st;
+    if (nslab <= 1) {
+      if ((st = pass(0, false, -1)) || (st = pass(1, wr, -1))) return st;
+      return MCG_OK;
+    }
+    if ((st = pass(0, false, 0)) || (st = pass(0, false, 1))) return st;
+    for (int k = 2; k < nslab; k++)
+      if ((st = pass(0, false, k)) || (st = pass(1, wr, k - 1))) return st;
+    if ((st = pass(1, wr, nslab - 1)) || (st = pass(1, wr, 0))) return st;
+    return MCG_OK;
+  }
   mcg_status sweep(bool reunit_first) {
     if (reunit_first) {
       HIPCHK(launch_reunit<T>(bs, c12, dD, B, total_blocks, true, s));
       HIPCHK(launch_rederive<T>(bs, c12, dD, B, total_blocks, true, s));
       HIPCHK(launch_book<T>(dD, B, BOOK_RESET, s));
     }
-    HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, total_blocks, 0, omega, false, true, s));
-    HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, total_blocks, 1, omega, true, true, s));
+    mcg_status st;
+    if ((st = halfsweeps(true))) return st;
     HIPCHK(launch_book<T>(dD, B, BOOK_CHECK, s));
     return MCG_OK;
   }
@@ -241,12 +294,13 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     hS[b] = f;
     total += nb;
   }
+  FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
+  run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
   HIPCHK(hipStreamSynchronize(s));
 
-  FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
   if (c12)
     for (int b = 0; b < B; b++)
       HIPCHK(launch_gauge_form(geom_of(U[b].d), G[b].ptr, (double *)ctx->G12[b].p, true, s));
@@ -695,8 +749,12 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   memset(hD, 0, sizeof(LatDesc<T>));
   hD->g = g;
   hD->nblk = nb;
+  hD->nslab = 1;
   hD->W = c12 ? (V2<T> *)ctx->w12.p : (V2<T> *)W->ptr;
   hD->G = c12 ? (double2 *)ctx->g12.p : (double2 *)G->ptr;
+  FixRun<T> run{ctx, s, 1, variant, variant_block(variant), nb, c12, ctx->desc.p, omega};
+  run.gated = false;
+  if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
     HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s));
@@ -706,8 +764,8 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
     HIPCHK(launch_links_form<T>(g, W->ptr, ctx->w12.p, true, s));
     HIPCHK(launch_gauge_form(g, G->ptr, (double *)ctx->g12.p, true, s));
   }
-  for (int k = 0; k < 2 * n; k++)
-    HIPCHK(launch_halfsweep<T>(variant, c12, ctx->desc.p, 1, nb, k & 1, omega, false, false, s));
+  for (int k = 0; k < n; k++)
+    if ((st = run.halfsweeps(false))) return st;
   if (c12) {
     HIPCHK(launch_links_form<T>(g, ctx->w12.p, W->ptr, false, s));
     HIPCHK(launch_gauge_form(g, (const double *)ctx->g12.p, G->ptr, false, s));
@@ -828,6 +886,11 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->c12 = value != 0;
     return MCG_OK;
   }
+  if (option == MCG_OPT_SLABS) {
+    if (value < 1 || value > MAX_SLABS) return fail(ctx, MCG_EINVAL, "MCG_OPT_SLABS takes 1..%d", MAX_SLABS);
+    ctx->nslab = value;
+    return MCG_OK;
+  }
   return fail(ctx, MCG_EINVAL, "unknown option %d", option);
 }
 
@@ -836,6 +899,10 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   if (!value) return fail(ctx, MCG_EINVAL, "NULL output");
   if (option == MCG_OPT_TWO_ROW) {
     *value = ctx->c12 ? 1 : 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_SLABS) {
+    *value = ctx->nslab;
     return MCG_OK;
   }
   return fail(ctx, MCG_EINVAL, "unknown option %d", option);

@@ -14,6 +14,24 @@ __device__ __forceinline__ int find_field(const LatDesc<T> *__restrict__ D, int 
   return b;
 }
 
+// The field of this grid block and the block's index within the field: the
+// whole-field mapping for slab < 0, else the chunk of slab `slab`.  A field
+// whose chunk is empty has the same start as the next one and is skipped.
+template <typename T>
+__device__ __forceinline__ int block_of(const LatDesc<T> *__restrict__ D, int B, int slab, int &local) {
+  if (slab < 0) {
+    const int b = find_field(D, B);
+    local = (int)blockIdx.x - D[b].blk0;
+    return b;
+  }
+  int b = 0;
+  for (int i = 1; i < B; i++)
+    if ((int)blockIdx.x >= D[i].sblk0[slab]) b = i;
+  const int lo = D[b].nslab > 1 ? (slab * D[b].nblk) / D[b].nslab : 0;
+  local = lo + (int)blockIdx.x - D[b].sblk0[slab];
+  return b;
+}
+
 // ---------------------------------------------------------- local update
 // One SU(2) subgroup step on rows/columns (I, J): the subgroup element
 // s = a0 + i a.sigma maximising Re tr(s Y) is a* = v/|v| with
@@ -77,15 +95,17 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // the lattice once (each link joins one even and one odd site).
 // C12: W and G are stored as their first two rows; only those rows stay in
 // registers and row 2 is rebuilt where a product needs it.
+// slab >= 0: this launch covers only that slab's chunk of every field (see LatDesc).
 template <typename T, int BS, bool WR, int OCC, bool C12>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
-                                                       T omega, int gated) {
+                                                       T omega, int gated, int slab) {
   using WS = typename FixStore<T, C12>::W;
   using GS = typename FixStore<T, C12>::G;
-  const int b = find_field(D, B);
+  int lb;
+  const int b = block_of(D, B, slab, lb);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
-  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  const int h = lb * BS + (int)threadIdx.x;
   double r = 0.0;
   if (h < d.g.Vh) {
     const WS W{d.W, d.g.Vh};
@@ -153,7 +173,7 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
   }
   if (WR) {
     const double s = block_sum<BS>(r);
-    if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+    if (threadIdx.x == 0) d.part[lb] = s;
   }
 }
 

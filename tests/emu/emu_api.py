@@ -252,3 +252,11 @@ def wilson_loops(U, vecs, rmax, tmax):
     check(lib().mcg_wilson_loops(ctx(), C.byref(f), len(v), v.ctypes.data_as(C.POINTER(C.c_int32)), rmax, tmax,
                                  W.ctypes.data_as(C.POINTER(C.c_double)), None))
     return W
+
+
+def set_slabs(n):
+    check(lib().mcg_set_option(ctx(), 2, n))
+
+
+def set_variant(prec, v):
+    check(lib().mcg_set_variant(ctx(), prec, v))

@@ -175,16 +175,43 @@ def scenario_loops(L, prec):
         check(np.abs(got - want).max() < (1e-13 if prec == 0 else 2e-6), f"wilson loops {vecs}")
 
 
+def scenario_slabs(prec):
+    """Slab-pipelined half-sweeps give the bits of whole half-sweeps."""
+    L1, L2 = (4, 4, 4, 32), (2, 2, 2, 2)
+    U1, U2 = rounded(field(L1, 2060), prec), rounded(field(L2, 2061), prec)
+    G1 = S.haar_gauge(L1, S.sub_seed(2062))
+    E.set_variant(prec, 0)  # 64-thread blocks: 16 blocks per half-sweep of L1
+    ref = None
+    for n in (1, 2, 3, 8):
+        E.set_slabs(n)
+        G, info = E.fix(E.links(U1, prec), E.gauge(G1), tol=-1.0, max_sweeps=7, reunit_every=3, check_every=2)
+        infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], [E.gauge_identity(L2), E.gauge(G1)],
+                            [-1.0, -1.0], [5, 7], reunit_every=3, check_every=2)
+        W, Gd = E.links(U1, prec), E.gauge(G1)
+        E.sweeps(W, Gd, 2)
+        got = (E.host_gauge(G), info["traj"], infos[0]["traj"], infos[1]["traj"], E.host_links(W), E.host_gauge(Gd))
+        if ref is None:
+            ref = got
+            check(np.array_equal(got[1], got[3]), "batch equals single")
+        else:
+            check(all(np.array_equal(a, b) for a, b in zip(got, ref)), f"slabs {n} differ from whole half-sweeps")
+    E.set_slabs(1)
+    E.set_variant(prec, 2)
+
+
 def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
     names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward",
-                             "loops"]
+                             "loops", "slabs"]
     for name in names:
         if name == "batch":
             for prec in (0, 1):
                 scenario_batch(prec)
         elif name == "planted":
             scenario_planted()
+        elif name == "slabs":
+            for prec in (0, 1):
+                scenario_slabs(prec)
         elif name == "loops":
             for L in ((4, 4, 4, 4), (2, 2, 2, 2)):
                 for prec in (0, 1):

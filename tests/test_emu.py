@@ -10,7 +10,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "emu")
-GROUPS = ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward", "loops"]
+GROUPS = ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward", "loops",
+          "slabs"]
 
 
 def _stale(lib, srcdirs):

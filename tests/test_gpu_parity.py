@@ -296,3 +296,34 @@ def test_synth_gpu_is_bitwise_cpu(S, g):
         b = S.heatbath_field_gpu(L, S.sub_seed(1040), 5.7, n).cpu().numpy()
         assert np.array_equal(a, b)
         assert np.array_equal(S.haar_gauge(L, 5, 3), S.haar_gauge_gpu(L, 5, 3).cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
+    """Half-sweeps run slab by slab (several slab counts, a batch mixing a
+    split and an unsplit field) give the bits of whole half-sweeps."""
+    L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
+    U1 = g.rounded(field(S, L1, 1050), prec)
+    U2 = g.rounded(field(S, L2, 1051), prec)
+    G1 = S.haar_gauge(L1, S.sub_seed(1052))
+    ref = None
+    try:
+        for n in (1, 2, 5, 8):
+            api.set_slabs(n)
+            G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=60, reunit_every=25,
+                              check_every=20, want_traj=True)
+            Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)], [api.gauge_identity(L2), g.gauge(G1)],
+                                      tol=-1.0, max_sweeps=[40, 60],
+                                      reunit_every=25, check_every=20, want_traj=True)
+            W, Gd = g.links(U1, prec), g.gauge(G1)
+            api.sweeps(W, Gd, 3)
+            got = [g.host_gauge(G), info["traj"], infos[0]["traj"], infos[1]["traj"], g.host_gauge(Gb[1]),
+                   g.host_links(W), g.host_gauge(Gd)]
+            if ref is None:
+                ref = got
+                assert np.array_equal(got[1], got[3]) and np.array_equal(got[0], got[4])
+            else:
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), n
+    finally:
+        api.set_slabs(1)
