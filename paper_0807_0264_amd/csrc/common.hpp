@@ -422,7 +422,16 @@ template <int BS> __device__ __forceinline__ double block_min(double v) {
 // in order, then block_sum.  Result valid in thread 0.
 template <int BS> __device__ __forceinline__ double sum_partials(const double *p, int n) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+  int i = threadIdx.x;
+  // eight loads in flight per step; the additions keep the order i, i+BS, i+2BS, ...
+  for (; i + 7 * BS < n; i += 8 * BS) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = p[i + k * BS];
+#pragma unroll
+    for (int k = 0; k < 8; k++) s += v[k];
+  }
+  for (; i < n; i += BS) s += p[i];
   return block_sum<BS>(s);
 }
 

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <barrier>
+#include <condition_variable>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -133,6 +134,53 @@ inline void submit(hipStream_t s, std::function<void()> f) {
   else
     f();
 }
+// Persistent lane threads: run(n, f) calls f(t) on threads t = 0..n-1 and
+// returns when all have finished (threads are created once and reused).
+class LanePool {
+ public:
+  static LanePool &get() {
+    static LanePool *p = new LanePool;  // never destroyed: idle workers may outlive main
+    return *p;
+  }
+  void run(unsigned n, const std::function<void(unsigned)> &f) {
+    std::unique_lock<std::mutex> lk(m_);
+    while (th_.size() < n) {
+      const unsigned id = (unsigned)th_.size();
+      th_.emplace_back([this, id] { work(id); });
+      th_.back().detach();
+    }
+    task_ = &f;
+    n_ = n;
+    left_ = n;
+    gen_++;
+    go_.notify_all();
+    done_.wait(lk, [this] { return left_ == 0; });
+    task_ = nullptr;
+  }
+
+ private:
+  void work(unsigned id) {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(m_);
+    for (;;) {
+      go_.wait(lk, [&] { return gen_ != seen; });
+      seen = gen_;
+      if (id >= n_) continue;
+      const std::function<void(unsigned)> *f = task_;
+      lk.unlock();
+      (*f)(id);
+      lk.lock();
+      if (--left_ == 0) done_.notify_one();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable go_, done_;
+  std::vector<std::thread> th_;
+  const std::function<void(unsigned)> *task_ = nullptr;
+  unsigned n_ = 0, left_ = 0;
+  uint64_t gen_ = 0;
+};
+
 template <typename F> void run_grid(dim3 grid, dim3 block, F body) {
   const unsigned nthreads = block.x * block.y * block.z;
   for (unsigned bz = 0; bz < grid.z; bz++)
@@ -140,19 +188,16 @@ template <typename F> void run_grid(dim3 grid, dim3 block, F body) {
       for (unsigned bx = 0; bx < grid.x; bx++) {
         std::barrier<> bar((std::ptrdiff_t)nthreads);
         std::vector<unsigned char> slots(8 * nthreads);
-        std::vector<std::thread> th;
-        th.reserve(nthreads);
-        for (unsigned t = 0; t < nthreads; t++)
-          th.emplace_back([&, t] {
-            t_block = dim3(bx, by, bz);
-            t_thread = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
-            t_bdim = block;
-            t_gdim = grid;
-            t_ctx = BlockCtx{&bar, &slots};
-            body();
-            bar.arrive_and_drop();
-          });
-        for (auto &x : th) x.join();
+        const std::function<void(unsigned)> lane = [&](unsigned t) {
+          t_block = dim3(bx, by, bz);
+          t_thread = dim3(t % block.x, (t / block.x) % block.y, t / (block.x * block.y));
+          t_bdim = block;
+          t_gdim = grid;
+          t_ctx = BlockCtx{&bar, &slots};
+          body();
+          bar.arrive_and_drop();
+        };
+        LanePool::get().run(nthreads, lane);
       }
 }
 }  // namespace emu
