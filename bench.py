@@ -195,6 +195,58 @@ def wilson_loop_run(api, torch, U, G=None, reps=3):
                 fields=out)
 
 
+# FP32 flop per link of one smearing step, counted from the operations: stout = 12 staple products
+# + C U^dag + Q^2 + exp(iQ) U = 15 complex 3x3 products (198 flop each) plus sums and the exponential's
+# scalar series (~0.3 kflop); over-improved adds 18 rectangle staples of 4 products each (87 products)
+SMEAR_FLOP_PER_LINK = {"stout": 15 * 198 + 300, "over-improved": 87 * 198 + 300}
+FP32_VECTOR_PEAK = 157.3e12
+
+
+def smear_run(api, torch, U, nsteps=10, reps=3):
+    """One smearing step of the 32^3x64 field, stout (rho 0.1) and
+    over-improved (rho 0.06, eps -0.25), timed with HIP events."""
+    out = {}
+    for name, rho, eps in (("stout", 0.1, 1.0), ("over-improved", 0.06, -0.25)):
+        S = api.smear(U, rho, eps, 1)  # warm-up and output allocation
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.smear(U, rho, eps, nsteps, out=S)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / (reps * nsteps)
+        links = 4 * api.volume(U.L)
+        tf = links * SMEAR_FLOP_PER_LINK[name] / (ms * 1e-3) / 1e12
+        out[name] = dict(ms_per_step=round(ms, 4), flop_per_link=SMEAR_FLOP_PER_LINK[name],
+                         tflops=round(tf, 2), frac_fp32_peak=round(tf * 1e12 / FP32_VECTOR_PEAK, 4))
+        del S
+    return out
+
+
+def backward_run(api, torch, synth, reps=3):
+    """Gradient of R(S_20(U)^{G*}) (over-improved, rho 0.06, eps -0.25,
+    checkpoint every 5 steps) on a 16^4 heatbath field, FP32 links."""
+    L = (16, 16, 16, 16)
+    U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(1, 0), 5.7, 50), 1)
+    G, _ = api.fix(api.smear(U, 0.06, -0.25, 20), None, tol=1e-7, max_sweeps=5000)
+    api.smear_mcg_backward(U, 0.06, -0.25, 20, G, 5)  # warm-up and scratch allocation
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(reps):
+        api.smear_mcg_backward(U, 0.06, -0.25, 20, G, 5)
+    torch.cuda.synchronize()
+    ms = 1000 * (time.time() - t0) / reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    api.smear(U, 0.06, -0.25, 20)
+    e1.record()
+    e1.synchronize()
+    fwd = e0.elapsed_time(e1)
+    return dict(workload="16^4, over-improved rho=0.06 eps=-0.25, n=20, checkpoint every 5, FP32",
+                ms=round(ms, 3), forward_smear_ms=round(fwd, 3), ratio_to_forward=round(ms / fwd, 2))
+
+
 def copy_ceiling(torch, nbytes=1 << 30, reps=10):
     """Device-to-device copy rate of the runtime's copy kernel (bytes read +
     written), the practical ceiling that an HBM-bound kernel is compared with."""
@@ -228,15 +280,16 @@ def one_step(api, fields, tol=1e-7, max_sweeps=5000):
     return out
 
 
-def roofline(api, torch, U, nsweeps=100):
+def roofline(api, torch, U, nsweeps=200, runs=5):
     """Average duration of the half-sweep kernel at 32^3x64 (FP32 links, FP64
     G), from HIP events on the stream the kernels are launched on (the
     library launches on torch's current stream).  A call of api.sweeps also
     converts W and G to and from the storage form; timing n + 20 and 20
-    sweeps and taking the difference leaves 2n half-sweep launches alone."""
+    sweeps and taking the difference leaves 2n half-sweep launches alone.
+    The median of `runs` such measurements after 10 warm-up sweeps."""
     W = U.clone()
     G = api.gauge_identity(U.L)
-    api.sweeps(W, G, 5)  # warm-up
+    api.sweeps(W, G, 10)  # warm-up
     torch.cuda.synchronize()
 
     def timed(n):
@@ -247,7 +300,8 @@ def roofline(api, torch, U, nsweeps=100):
         e1.synchronize()
         return e0.elapsed_time(e1)
 
-    ms = (timed(nsweeps + 20) - timed(20)) / (2 * nsweeps)
+    import statistics
+    ms = statistics.median((timed(nsweeps + 20) - timed(20)) / (2 * nsweeps) for _ in range(runs))
     two_row = api.get_two_row()
     bps = BYTES_PER_SITE_UPDATE[two_row]
     site_updates = api.volume(U.L) // 2
@@ -282,9 +336,26 @@ def cpu_baseline(U64, target_s=15.0):
         O.halfsweep_inplace(W, G, (k + 1) & 1, 1.7)
     dt = time.time() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same half-sweep on one thread (the oracle's OpenMP runtime is libgomp)
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(1)
+    t0 = time.time()
+    n1 = 0
+    while n1 < 2 or time.time() - t0 < 3.0:
+        O.halfsweep_inplace(W, G, n1 & 1, 1.7)
+        n1 += 1
+    dt1 = time.time() - t0
+    gomp.omp_set_num_threads(cores)
+    model = ""
+    try:
+        model = next(ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=round(n * (V // 2) / dt, 1), unit="site-updates/s", cores=cores, kind="oracle",
                 sample=f"{n} FP64 oracle half-sweeps of the 32^3x64 field ({V // 2} site-updates each), "
-                       f"{dt:.1f} s")
+                       f"{dt:.1f} s, {cores} OpenMP threads on {os.cpu_count()} visible CPUs ({model})",
+                single_thread_value=round(n1 * (V // 2) / dt1, 1))
 
 
 def profile_run(api, torch, synth):
@@ -316,6 +387,8 @@ def main():
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--profile-loops", action="store_true", help="short Wilson-loop run for rocprofv3")
     ap.add_argument("--profile-step", action="store_true", help="one benchmark step for rocprofv3")
+    ap.add_argument("--profile-smear", action="store_true", help="smearing steps at 32^3x64 for rocprofv3")
+    ap.add_argument("--profile-backward", action="store_true", help="one backward pass at 16^4 for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the workload is one MI355X's share of the job, and "
@@ -335,6 +408,14 @@ def main():
         r = one_step(api, fields)
         torch.cuda.synchronize()
         print(json.dumps(dict(profile="done", sweeps=[(x["sweeps_smeared"], x["sweeps"]) for x in r])))
+        return
+    if args.profile_smear:
+        L = LATTICES[0]
+        U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(5, 0), 5.7, 50), 1)
+        print(json.dumps(dict(profile="done", lattice=L, smear=smear_run(api, torch, U, reps=1))))
+        return
+    if args.profile_backward:
+        print(json.dumps(dict(profile="done", backward=backward_run(api, torch, synth, reps=1))))
         return
     if args.profile_loops:
         L = LATTICES[2]
@@ -367,6 +448,10 @@ def main():
     roof["copy_ceiling_GBps"] = copy_ceiling(torch)
     log(f"roofline: {roof}")
     gribov = None if args.no_gribov else gribov_copies(api, synth, torch, fields[2][1])
+    smear = smear_run(api, torch, fields[0][1])
+    log(f"smear: {smear}")
+    backward = backward_run(api, torch, synth)
+    log(f"backward: {backward}")
     G20, _ = api.fix(fields[2][1], None, tol=1e-7, max_sweeps=5000)
     loops = wilson_loop_run(api, torch, fields[2][1], G20)
     log(f"wilson loops: {loops['fields']}")
@@ -386,6 +471,8 @@ def main():
     if gribov is not None:
         line["gribov_copies"] = gribov
     line["wilson_loops"] = loops
+    line["smear"] = smear
+    line["backward"] = backward
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(fields[0][2])
     print(json.dumps(line), flush=True)

@@ -186,18 +186,36 @@ def main(argv=None):
     ap.add_argument("--beta", type=float, default=5.7)
     ap.add_argument("--prec", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--compare", action="store_true",
+                    help="run every configuration in both precisions and report the FP32 - FP64 differences")
     ap.add_argument("--json", action="store_true", help="print the raw per-configuration results as JSON")
     a = ap.parse_args(argv)
     L = tuple(int(v) for v in a.lattice.split(","))
-    prec = 1 if a.prec == "fp32" else 0
-    results = []
+    precs = (1, 0) if a.compare else ((1,) if a.prec == "fp32" else (0,))
+    results = {p: [] for p in precs}
     for c in range(a.configs):
-        U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(11, c), a.beta, 50), prec)
-        results.append(run_levels(U, tol=a.tol))
+        U64 = synth.heatbath_field_gpu(L, synth.sub_seed(11, c), a.beta, 50)
+        # both precisions start from the same (FP32-rounded when comparing) values
+        if a.compare:
+            U64 = U64.to(torch.complex64).to(torch.complex128)
+        for p in precs:
+            results[p].append(run_levels(api.to_links(U64, p), tol=a.tol))
         torch.cuda.synchronize()
         print(f"configuration {c}: " + ", ".join(f"{r['level']}: R {r['R']:.5f} v {r['vortices']}"
-                                                 for r in results[-1]), flush=True)
-    print(json.dumps(results) if a.json else format_tables(results), flush=True)
+                                                 for r in results[precs[0]][-1]), flush=True)
+    for p in precs:
+        print(f"\n{'FP32' if p == 1 else 'FP64'} links", flush=True)
+        print(json.dumps(results[p]) if a.json else format_tables(results[p]), flush=True)
+    if a.compare:
+        print("\nFP32 - FP64 per result (mean |difference| over configurations; sweeps: mean signed difference)")
+        for k, lv in enumerate(results[1][0]):
+            d = [(x[k], y[k]) for x, y in zip(results[1], results[0])]
+            dRs = [abs(x["R_smeared"] - y["R_smeared"]) for x, y in d if x["R_smeared"] is not None]
+            print(f"{lv['level']:>6}: |dR| {sum(abs(x['R'] - y['R']) for x, y in d) / len(d):.2e}"
+                  + (f"  |dR_smeared| {sum(dRs) / len(dRs):.2e}" if dRs else "")
+                  + f"  |d vortex %| {sum(abs(x['vortices'] - y['vortices']) for x, y in d) / len(d) / lv['plaquettes'] * 100:.3f}"
+                  + f"  d sweeps {sum(x['sweeps'] + x['sweeps_smeared'] - y['sweeps'] - y['sweeps_smeared'] for x, y in d) / len(d):+.1f}",
+                  flush=True)
 
 
 if __name__ == "__main__":
