@@ -499,12 +499,9 @@ void or_smear(const int32_t L[4], const ocx *U, ocx *out, double rho,
  * so any g that raises Re tr(g X) cannot lower F.  g is built from three
  * SU(2) subgroup steps, each maximising Re tr(s Y) over the subgroup and
  * then over-relaxed towards the identity with weight omega. */
-void or_site_g(const ocx M[8 * 9], double omega, ocx g[9]) {
-  ocx X[9], Y[9];
-  m_zero(X);
-  for (int k = 0; k < 8; k++) m_axpy(conj(m_tr(M + 9 * k)), M + 9 * k, X);
-  m_copy(Y, X);
-  m_ident(g);
+/* the three SU(2) subgroup steps (0,1), (1,2), (0,2): each left-multiplies Y
+ * and g by the over-relaxed maximiser s of Re tr(s Y) on that subgroup */
+static void subgroup_steps(ocx Y[9], ocx g[9], double omega) {
   static const int SUB[3][2] = {{0, 1}, {1, 2}, {0, 2}};
   for (int q = 0; q < 3; q++) {
     int i = SUB[q][0], j = SUB[q][1];
@@ -530,6 +527,36 @@ void or_site_g(const ocx M[8 * 9], double omega, ocx g[9]) {
   }
 }
 
+void or_site_g(const ocx M[8 * 9], double omega, ocx g[9]) {
+  ocx X[9], Y[9];
+  m_zero(X);
+  for (int k = 0; k < 8; k++) m_axpy(conj(m_tr(M + 9 * k)), M + 9 * k, X);
+  m_copy(Y, X);
+  m_ident(g);
+  subgroup_steps(Y, g, omega);
+}
+
+/* Re-linearisation hits: hit 1 is or_site_g; each further hit linearises the
+ * local functional sum_k |tr(g' M_k)|^2 at the current g,
+ * X_g = sum_k conj(tr(g M_k)) M_k, and runs the subgroup steps on Y = g X_g,
+ * continuing g (g' = s g raises Re tr(g' X_g) = Re tr(s Y)); each hit is again
+ * a minorise-maximise step. */
+void or_site_g_hits(const ocx M[8 * 9], double omega, int hits, ocx g[9]) {
+  or_site_g(M, omega, g);
+  for (int h = 1; h < hits; h++) {
+    ocx X[9], Y[9];
+    m_zero(X);
+    for (int k = 0; k < 8; k++) {
+      ocx gm[9];
+      m_mul(g, M + 9 * k, gm);
+      m_axpy(conj(m_tr(gm)), M + 9 * k, X);
+    }
+    m_mul(g, X, Y);
+    subgroup_steps(Y, g, omega);
+  }
+}
+
+/* the eight links at x: W_mu(x), then W_mu(x - mu)^dagger */
 static void gather8(const lat_t *lt, const ocx *W, int64_t x, ocx M[72]) {
   for (int mu = 0; mu < 4; mu++) {
     m_copy(M + 9 * mu, link(W, x, mu));
@@ -548,13 +575,17 @@ void or_site_g_at(const int32_t L[4], const ocx *W, int64_t site,
 /* update every site of one parity; such sites share no link */
 void or_halfsweep(const int32_t L[4], ocx *W, ocx *G, int parity,
                   double omega) {
+  or_halfsweep_hits(L, W, G, parity, omega, 1);
+}
+void or_halfsweep_hits(const int32_t L[4], ocx *W, ocx *G, int parity,
+                       double omega, int hits) {
   lat_t lt = mklat(L);
 #pragma omp parallel for schedule(static)
   for (int64_t x = 0; x < lt.V; x++) {
     if (parity_of(&lt, x) != parity) continue;
     ocx M[72], g[9], gd[9];
     gather8(&lt, W, x, M);
-    or_site_g(M, omega, g);
+    or_site_g_hits(M, omega, hits, g);
     m_adj(g, gd);
     for (int mu = 0; mu < 4; mu++) {
       m_mul_left(g, link_w(W, x, mu));
@@ -600,6 +631,16 @@ static void reunit_all(const lat_t *lt, ocx *G) {
 int or_mcg_fix(const int32_t L[4], const ocx *U, ocx *G, double tol,
                int32_t max_sweeps, double omega, int32_t reunit_every,
                int32_t start_sweep, double *traj, or_fix_result *res) {
+  return or_mcg_fix_v(L, U, G, tol, max_sweeps, omega, reunit_every,
+                      start_sweep, 1, 1, traj, res);
+}
+/* variants of the update rule: `hits` re-linearisation hits per site visit;
+ * the stop test only after sweeps whose global number (start_sweep + k) is a
+ * multiple of stop_every */
+int or_mcg_fix_v(const int32_t L[4], const ocx *U, ocx *G, double tol,
+                 int32_t max_sweeps, double omega, int32_t reunit_every,
+                 int32_t start_sweep, int32_t hits, int32_t stop_every,
+                 double *traj, or_fix_result *res) {
   lat_t lt = mklat(L);
   ocx *W = malloc((size_t)lt.V * 36 * sizeof(ocx));
   or_apply_gauge(L, U, G, W);
@@ -614,13 +655,13 @@ int or_mcg_fix(const int32_t L[4], const ocx *U, ocx *G, double tol,
       or_apply_gauge(L, U, G, W);
       Rprev = or_functional(L, W);
     }
-    or_halfsweep(L, W, G, 0, omega);
-    or_halfsweep(L, W, G, 1, omega);
+    or_halfsweep_hits(L, W, G, 0, omega, hits);
+    or_halfsweep_hits(L, W, G, 1, omega, hits);
     double R = or_functional(L, W);
     if (traj) traj[k] = R;
     dR = R - Rprev;
     done = k;
-    if (dR < tol) {
+    if (s % stop_every == 0 && dR < tol) {
       status = 0;
       break;
     }

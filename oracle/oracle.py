@@ -58,11 +58,15 @@ def _declare(l):
         "or_smear_step": (None, [_I4, _P, _P, C.c_double, C.c_double]),
         "or_smear": (None, [_I4, _P, _P, C.c_double, C.c_double, C.c_int]),
         "or_site_g": (None, [_P, C.c_double, _P]),
+        "or_site_g_hits": (None, [_P, C.c_double, C.c_int, _P]),
+        "or_halfsweep_hits": (None, [_I4, _P, _P, C.c_int, C.c_double, C.c_int]),
         "or_site_g_at": (None, [_I4, _P, C.c_int64, C.c_double, _P]),
         "or_halfsweep": (None, [_I4, _P, _P, C.c_int, C.c_double]),
         "or_theta": (C.c_double, [_I4, _P]),
         "or_mcg_fix": (C.c_int, [_I4, _P, _P, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                  C.c_int32, _P, C.POINTER(FixResult)]),
+        "or_mcg_fix_v": (C.c_int, [_I4, _P, _P, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                   C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(FixResult)]),
         "or_center_project": (None, [_I4, _P, _P, _P, _P]),
         "or_count_vortices": (None, [_I4, _P, _P, _P, _P, _P]),
         "or_vortex_field": (None, [_I4, _P, _P, _P, C.c_int, _P]),
@@ -197,6 +201,14 @@ def site_g(M, omega):
     return g
 
 
+def site_g_hits(M, omega, hits):
+    """site_g with `hits` re-linearisation hits (hits = 1 is site_g)."""
+    M = _c128(M)
+    g = np.empty((3, 3), np.complex128)
+    lib().or_site_g_hits(_ptr(M), omega, int(hits), _ptr(g))
+    return g
+
+
 def site_g_at(W, site, omega):
     W = _c128(W)
     g = np.empty((3, 3), np.complex128)
@@ -204,10 +216,13 @@ def site_g_at(W, site, omega):
     return g
 
 
-def halfsweep(W, G, parity, omega):
+def halfsweep(W, G, parity, omega, hits=1):
     """In place on copies; returns (W', G')."""
     W, G = _c128(W).copy(), _c128(G).copy()
-    lib().or_halfsweep(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega)
+    if hits == 1:
+        lib().or_halfsweep(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega)
+    else:
+        lib().or_halfsweep_hits(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega, int(hits))
     return W, G
 
 
@@ -229,15 +244,21 @@ def identity_gauge(L):
 
 
 def mcg_fix(U, G0=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50,
-            start_sweep=0, want_traj=False):
-    """Returns (G, result dict, trajectory or None)."""
+            start_sweep=0, want_traj=False, hits=1, stop_every=1):
+    """Returns (G, result dict, trajectory or None).  hits: re-linearisation
+    hits per site visit; stop_every: the stop test only after sweeps whose
+    global number is a multiple of it."""
     U = _c128(U)
     L = dims_of(U)
     G = identity_gauge(L) if G0 is None else _c128(G0).copy()
     traj = np.zeros(max_sweeps + 1) if want_traj else None
     res = FixResult()
-    lib().or_mcg_fix(_dims(L), _ptr(U), _ptr(G), tol, int(max_sweeps), omega,
-                     int(reunit_every), int(start_sweep), _ptr(traj), C.byref(res))
+    if hits == 1 and stop_every == 1:
+        lib().or_mcg_fix(_dims(L), _ptr(U), _ptr(G), tol, int(max_sweeps), omega,
+                         int(reunit_every), int(start_sweep), _ptr(traj), C.byref(res))
+    else:
+        lib().or_mcg_fix_v(_dims(L), _ptr(U), _ptr(G), tol, int(max_sweeps), omega, int(reunit_every),
+                           int(start_sweep), int(hits), int(stop_every), _ptr(traj), C.byref(res))
     info = dict(R=res.R, dR=res.dR, theta=res.theta, sweeps=res.sweeps, status=res.status)
     if traj is not None:
         traj = traj[: res.sweeps + 1].copy()
