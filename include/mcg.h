@@ -224,6 +224,18 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * bit-identical to whole half-sweeps; the gain is that a slab's links are
  * re-read while they may still sit in the device's last-level cache. */
 #define MCG_OPT_SLABS 2
+/* Variants of the update rule (both default 1, the method as in mcg_fix):
+ * MCG_OPT_HITS (1..16): re-linearisation hits per site visit of mcg_fix,
+ * mcg_fix_batch, mcg_sweeps and mcg_halfsweep.  After the first update g,
+ * each further hit linearises sum_k |tr(g' M_k)|^2 at the current g,
+ * X_g = sum_k conj(tr(g M_k)) M_k, and applies the three over-relaxed
+ * subgroup steps to g X_g, continuing g (hits > 1 run with 256-thread
+ * blocks whatever the tuned variant).
+ * MCG_OPT_STOP_EVERY (1..10^6): the stop test dR < tol of mcg_fix and
+ * mcg_fix_batch is applied only after sweeps whose global number
+ * (start_sweep + k) is a multiple of this, e.g. 50 for whole blocks. */
+#define MCG_OPT_HITS 3
+#define MCG_OPT_STOP_EVERY 4
 mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value);
 mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value);
 

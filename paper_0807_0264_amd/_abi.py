@@ -14,6 +14,8 @@ MCG_F64, MCG_F32 = 0, 1
 MCG_NUM_VARIANTS = 6
 MCG_OPT_TWO_ROW = 1
 MCG_OPT_SLABS = 2
+MCG_OPT_HITS = 3
+MCG_OPT_STOP_EVERY = 4
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 

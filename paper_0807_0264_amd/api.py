@@ -402,6 +402,23 @@ def set_slabs(n, device=None):
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SLABS, int(n)), ctx)
 
 
+def set_update_variant(hits=1, stop_every=1, device=None):
+    """Update-rule variants of the fixing loop: `hits` re-linearisation hits
+    per site visit, and the stop test only after sweeps numbered by multiples
+    of `stop_every` (1, 1: the plain method)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_HITS, int(hits)), ctx)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_STOP_EVERY, int(stop_every)), ctx)
+
+
+def get_update_variant(device=None):
+    ctx = context(device)
+    h, s = C.c_int32(), C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_HITS, C.byref(h)), ctx)
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_STOP_EVERY, C.byref(s)), ctx)
+    return h.value, s.value
+
+
 def get_slabs(device=None):
     ctx = context(device)
     v = C.c_int32()

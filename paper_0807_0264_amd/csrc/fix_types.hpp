@@ -22,7 +22,8 @@ struct FixState {
   int32_t max_k;   // sweeps allowed in this call
   int32_t done;    // 1 once converged or out of sweeps: every gated kernel exits at once
   int32_t status;  // 0 converged, 1 not converged
-  int32_t pad0, pad1;
+  int32_t stop_every;   // the stop test only after sweeps whose global number is a multiple of it
+  int32_t start_sweep;  // global number of the sweep before this call's first
 };
 
 constexpr int MAX_SLABS = 16;

@@ -26,9 +26,20 @@ namespace mcg {
 // c12: working field and transform stored as two rows
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab) {
+                            bool withR, bool gated, hipStream_t s, int slab, int hits) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
+  if (hits > 1) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
+    if (bs != 256) return hipErrorInvalidValue;
+#define MCG_HM(WR, C) k_halfsweep<T, 256, WR, 1, C, true><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, hits)
+    if (c12) {
+      if (withR) MCG_HM(true, true); else MCG_HM(false, true);
+    } else {
+      if (withR) MCG_HM(true, false); else MCG_HM(false, false);
+    }
+#undef MCG_HM
+    return hipGetLastError();
+  }
 #define MCG_HS(WR, OCC, C)                                                                         \
   MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab)))
   if (c12) {
@@ -101,7 +112,7 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t, int);                                         \
+                                          hipStream_t, int, int);                                    \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
   template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \

@@ -39,6 +39,8 @@ struct mcg_ctx {
   size_t h_pinned_cap = 0;
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
+  int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
+  int stop_every = 1;  // stop test only after sweeps numbered by multiples of this (MCG_OPT_STOP_EVERY)
   int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
 };
 
@@ -191,10 +193,12 @@ template <typename T> struct FixRun {
   int nslab = 1;
   int grid[MAX_SLABS] = {};
   bool gated = true;
+  int hits = 1;
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
-    if (blocks > 0) HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab));
+    if (blocks > 0)
+      HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits));
     return MCG_OK;
   }
   // Even then odd half-sweep.  Slab by slab (n > 1), in the order E0 E1 [E(k) O(k-1)] for
@@ -254,7 +258,8 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
         return fail(ctx, MCG_EINVAL, "fields %d and %d share U and G", c, b);
   }
   const bool c12 = ctx->c12;
-  const int variant = ctx->variant[prec][c12], bs = variant_block(variant);
+  // re-linearisation hits run in one instantiation with 256-thread blocks (variant 2)
+  const int variant = ctx->hits > 1 ? 2 : ctx->variant[prec][c12], bs = variant_block(variant);
   if ((int)ctx->W.size() < B) {
     ctx->W.resize(B);
     ctx->G12.resize(B);
@@ -291,11 +296,14 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     memset(&f, 0, sizeof f);
     f.tol = opts[b].tol;
     f.max_k = opts[b].max_sweeps;
+    f.stop_every = ctx->stop_every;
+    f.start_sweep = s0;
     hS[b] = f;
     total += nb;
   }
   FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
   run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
+  run.hits = ctx->hits;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -736,7 +744,7 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
                                  hipStream_t s, int n = 1) {
   const Geom g = geom_of(W->d);
   const bool c12 = parity < 0 && ctx->c12;
-  const int variant = ctx->variant[W->prec][c12], nb = nblocks(g, variant_block(variant));
+  const int variant = ctx->hits > 1 ? 2 : ctx->variant[W->prec][c12], nb = nblocks(g, variant_block(variant));
   mcg_status st;
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
     return st;
@@ -754,10 +762,11 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   hD->G = c12 ? (double2 *)ctx->g12.p : (double2 *)G->ptr;
   FixRun<T> run{ctx, s, 1, variant, variant_block(variant), nb, c12, ctx->desc.p, omega};
   run.gated = false;
+  run.hits = ctx->hits;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
-    HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s));
+    HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s, -1, ctx->hits));
     return MCG_OK;
   }
   if (c12) {
@@ -891,6 +900,16 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->nslab = value;
     return MCG_OK;
   }
+  if (option == MCG_OPT_HITS) {
+    if (value < 1 || value > 16) return fail(ctx, MCG_EINVAL, "MCG_OPT_HITS takes 1..16");
+    ctx->hits = value;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_STOP_EVERY) {
+    if (value < 1 || value > 1000000) return fail(ctx, MCG_EINVAL, "MCG_OPT_STOP_EVERY takes 1..1000000");
+    ctx->stop_every = value;
+    return MCG_OK;
+  }
   return fail(ctx, MCG_EINVAL, "unknown option %d", option);
 }
 
@@ -903,6 +922,14 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   }
   if (option == MCG_OPT_SLABS) {
     *value = ctx->nslab;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_HITS) {
+    *value = ctx->hits;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_STOP_EVERY) {
+    *value = ctx->stop_every;
     return MCG_OK;
   }
   return fail(ctx, MCG_EINVAL, "unknown option %d", option);

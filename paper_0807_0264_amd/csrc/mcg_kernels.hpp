@@ -69,12 +69,17 @@ __device__ __forceinline__ void su2_step(M3<T> &Y, M3<T> &g, T omega) {
   }
 }
 
-// g from the linearisation X = sum_k conj(tr M_k) M_k: subgroups (0,1), (1,2), (0,2)
-template <typename T> __device__ __forceinline__ M3<T> local_update(M3<T> Y, T omega) {
-  M3<T> g = m_ident<T>();
+// the subgroup steps (0,1), (1,2), (0,2), each left-multiplying Y and g
+template <typename T> __device__ __forceinline__ void subgroup_steps(M3<T> &Y, M3<T> &g, T omega) {
   su2_step<T, 0, 1, true>(Y, g, omega);
   su2_step<T, 1, 2, true>(Y, g, omega);
   su2_step<T, 0, 2, false>(Y, g, omega);
+}
+
+// g from the linearisation X = sum_k conj(tr M_k) M_k
+template <typename T> __device__ __forceinline__ M3<T> local_update(M3<T> Y, T omega) {
+  M3<T> g = m_ident<T>();
+  subgroup_steps(Y, g, omega);
   return g;
 }
 
@@ -96,9 +101,12 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // C12: W and G are stored as their first two rows; only those rows stay in
 // registers and row 2 is rebuilt where a product needs it.
 // slab >= 0: this launch covers only that slab's chunk of every field (see LatDesc).
-template <typename T, int BS, bool WR, int OCC, bool C12>
+// MULTI: `hits` re-linearisation hits per site: after the first update each further hit
+// linearises sum_k |tr(g M_k)|^2 at the current g, X_g = sum_k conj(tr(g M_k)) M_k, and runs
+// the subgroup steps on g X_g, continuing g.
+template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
-                                                       T omega, int gated, int slab) {
+                                                       T omega, int gated, int slab, int hits = 1) {
   using WS = typename FixStore<T, C12>::W;
   using GS = typename FixStore<T, C12>::G;
   int lb;
@@ -145,7 +153,30 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       if constexpr (C12) third_row(bk);
       axpy_dag(trace(bk), bk, X);
     }
-    const M3<T> g = local_update<T>(X, omega);
+    M3<T> g = local_update<T>(X, omega);
+    if constexpr (MULTI) {
+      for (int it = 1; it < hits; it++) {
+        M3<T> Xh = m_zero<T>();
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+          M3<T> f = F[mu];
+          if constexpr (C12) third_row(f);
+          axpy(conj(trace(mul(g, f))), f, Xh);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+          M3<T> bk = Bk[mu];
+          if constexpr (C12) third_row(bk);
+          // M = bk^dag: conj(tr(g M)) M = conj(tr(g bk^dag)) bk^dag
+          cx<T> t{T(0), T(0)};
+#pragma unroll
+          for (int k = 0; k < 9; k++) t = t + mulc(g.e[k], bk.e[k]);
+          axpy_dag(conj(t), bk, Xh);
+        }
+        M3<T> Y = mul(g, Xh);
+        subgroup_steps(Y, g, omega);
+      }
+    }
 
 #pragma unroll
     for (int mu = 0; mu < 4; mu++) {
@@ -321,7 +352,7 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
     st->dR = dR;
     st->R_last = R;
     if (d.traj) d.traj[st->k] = R;
-    if (dR < st->tol) {
+    if (dR < st->tol && (st->start_sweep + st->k) % st->stop_every == 0) {
       st->done = 1;
       st->status = 0;
     } else if (st->k >= st->max_k) {

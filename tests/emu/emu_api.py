@@ -260,3 +260,8 @@ def set_slabs(n):
 
 def set_variant(prec, v):
     check(lib().mcg_set_variant(ctx(), prec, v))
+
+
+def set_update_variant(hits, stop_every):
+    check(lib().mcg_set_option(ctx(), 3, hits))
+    check(lib().mcg_set_option(ctx(), 4, stop_every))

@@ -327,3 +327,36 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
                     assert np.array_equal(a, b), n
     finally:
         api.set_slabs(1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 6, 6, 10)])
+def test_update_variants(S, O, g, api, L, prec):
+    """Re-linearisation hits and the block-wise stop test against the oracle."""
+    U = g.rounded(field(S, L, 1060), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1061))
+    try:
+        for hits, stop_every in ((2, 1), (3, 1), (1, 25), (2, 10)):
+            api.set_update_variant(hits, stop_every)
+            for two_row in (True, False):
+                api.set_two_row(two_row)
+                G, info = api.fix(g.links(U, prec), g.gauge(G0), tol=1e-6, max_sweeps=60, reunit_every=20,
+                                  check_every=7, want_traj=True)
+                Go, io, to = O.mcg_fix(U, G0, tol=1e-6, max_sweeps=60, reunit_every=20, want_traj=True, hits=hits,
+                                       stop_every=stop_every)
+                n = min(info["sweeps"], io["sweeps"]) + 1
+                assert (np.abs(info["traj"][:n] - to[:n]) / to[:n]).max() < TOL[prec]
+                if prec == 0:
+                    assert info["status"] == io["status"] and info["sweeps"] == io["sweeps"]
+                    assert np.abs(g.host_gauge(G) - Go).max() < 1e-10
+                if info["status"] == 0:
+                    assert info["sweeps"] % stop_every == 0
+            W, Gd = g.links(U, prec), g.gauge(G0)
+            api.sweeps(W, Gd, 2)
+            Wo, Ho = U.copy(), G0.copy()
+            for par in (0, 1, 0, 1):
+                Wo, Ho = O.halfsweep(Wo, Ho, par, 1.7, hits=hits)
+            assert np.abs(g.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 3e-5)
+    finally:
+        api.set_update_variant(1, 1)
+        api.set_two_row(True)
