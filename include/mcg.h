@@ -140,6 +140,14 @@ mcg_status mcg_gauge_identity(mcg_ctx *ctx, mcg_gauge *G, void *stream);
 /* Re-unitarise every G(x) (Gram-Schmidt on rows, third row conj(r0 x r1)). */
 mcg_status mcg_gauge_reunit(mcg_ctx *ctx, mcg_gauge *G, void *stream);
 
+/* ---- input validation --------------------------------------------------------------- */
+/* Largest |(M M^dagger - 1)_ij| over the links of U and over the matrices of
+ * G (either may be NULL; host outputs dev_U / dev_G nullable, +inf when an
+ * entry is NaN).  A field fresh from unitary data reads ~1e-7 in FP32 and
+ * ~1e-15 in FP64.  Synchronises the stream. */
+mcg_status mcg_unitarity(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, double *dev_U, double *dev_G,
+                         void *stream);
+
 /* ---- smearing (Sec. II.B; parameters of Sec. III) -------------------------- */
 /* n Jacobi steps U' = exp(TA(C U^dagger)) U with the staple sum
  *   C = rho sum_{nu != mu} [ (5-2eps)/3 (2 plaquette staples)
@@ -236,6 +244,18 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * (start_sweep + k) is a multiple of this, e.g. 50 for whole blocks. */
 #define MCG_OPT_HITS 3
 #define MCG_OPT_STOP_EVERY 4
+/* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
+ * transform (smear, apply_gauge, fix, fix_batch, center_project,
+ * vortex_field, wilson_loops, smear_mcg_backward) first checks them and
+ * returns MCG_EINPUT, with the deviation in mcg_last_error, unless
+ * max_ij |(U U^dagger - 1)_ij| <= 1e-6 (FP32 links) or 1e-10 (FP64 links and
+ * every G) and no entry is NaN.  Costs one extra read of the inputs and a
+ * stream synchronisation per call. */
+#define MCG_OPT_CHECK 5
+/* MCG_OPT_SCRATCH_LIMIT_MIB (>= 0, default 0 = none): the most device memory
+ * the context may hold as scratch; a call that would need more returns
+ * MCG_ENOMEM and leaves the context usable. */
+#define MCG_OPT_SCRATCH_LIMIT_MIB 6
 mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value);
 mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value);
 

@@ -16,6 +16,8 @@ MCG_OPT_TWO_ROW = 1
 MCG_OPT_SLABS = 2
 MCG_OPT_HITS = 3
 MCG_OPT_STOP_EVERY = 4
+MCG_OPT_CHECK = 5
+MCG_OPT_SCRATCH_LIMIT_MIB = 6
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 
@@ -77,6 +79,8 @@ SIGNATURES = {
                                 C.POINTER(C.c_double), _P]),
     "mcg_count_vortices": (_S, [_CTX, _P, Dims, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int64), _P]),
+    "mcg_unitarity": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double), _P]),
     "mcg_vortex_field": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P, C.c_int32, C.POINTER(Field), _P]),
     "mcg_wilson_loops": (_S, [_CTX, C.POINTER(Field), C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
                               C.POINTER(C.c_double), _P]),

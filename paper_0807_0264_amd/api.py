@@ -402,6 +402,32 @@ def set_slabs(n, device=None):
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SLABS, int(n)), ctx)
 
 
+def unitarity(U=None, G=None):
+    """(max |U U^dag - 1|, max |G G^dag - 1|) over all links / matrices (inf for NaN)."""
+    if U is None and G is None:
+        raise ValueError("need U or G")
+    ref = U if U is not None else G
+    ctx = context(ref.data.device.index)
+    f = U.abi() if U is not None else None
+    g = G.abi() if G is not None else None
+    du, dg = C.c_double(), C.c_double()
+    _check(A.load().mcg_unitarity(ctx, C.byref(f) if f is not None else None, C.byref(g) if g is not None else None,
+                                  C.byref(du), C.byref(dg), _stream()), ctx)
+    return du.value, dg.value
+
+
+def set_check(on=True, device=None):
+    """Validate input links and transforms in every call (MCG_EINPUT when not unitary or NaN)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_CHECK, 1 if on else 0), ctx)
+
+
+def set_scratch_limit_mib(mib, device=None):
+    """Cap the device scratch the context may hold (0: no cap)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SCRATCH_LIMIT_MIB, int(mib)), ctx)
+
+
 def set_update_variant(hits=1, stop_every=1, device=None):
     """Update-rule variants of the fixing loop: `hits` re-linearisation hits
     per site visit, and the stop test only after sweeps numbered by multiples

@@ -149,6 +149,37 @@ __global__ __launch_bounds__(256) void k_field_sum(Geom g, const V2<T> *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// max over the nmu matrices per site (4: links, 1: a gauge field, FP64) of max_ij |(M M^dag - 1)_ij|,
+// computed in FP64; a NaN anywhere in a matrix counts as +inf.  Per-block maxima into part.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unitarity(Geom g, const V2<T> *__restrict__ U, int nmu, double *part) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  double dev = 0.0;
+  if (h < g.Vh) {
+    const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+    for (int par = 0; par < 2; par++)
+      for (int mu = 0; mu < nmu; mu++) {
+        const M3<double> m = m_cvt<double>(L.load(mu, par, h));
+        const M3<double> p = mul_nd(m, m);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+          const double re = p.e[k].re - ((k % 4 == 0) ? 1.0 : 0.0), im = p.e[k].im;
+          const double a = fmax(fabs(re), fabs(im));
+          dev = (a == a) ? fmax(dev, a) : __builtin_huge_val();
+        }
+      }
+  }
+  const double mx = -block_min<256>(-dev);
+  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const double *part, int n, double *out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v = fmax(v, part[i]);
+  v = -block_min<256>(-v);
+  if (threadIdx.x == 0) *out = v;
+}
+
 __global__ __launch_bounds__(256) void k_final_sum(const double *part, int n, double scale, double *out) {
   const double s = sum_partials<256>(part, n);
   if (threadIdx.x == 0) *out = s * scale;

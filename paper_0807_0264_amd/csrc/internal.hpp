@@ -63,6 +63,10 @@ hipError_t launch_center_project(const Geom &g, const void *U, const double *G, 
 hipError_t launch_count_vortices(const Geom &g, const int8_t *Z, unsigned long long *counts,
                                  hipStream_t s);
 
+// max_ij |(M M^dag - 1)_ij| over all matrices (nmu per site; NaN -> inf) into *out (device)
+template <typename T>
+hipError_t launch_unitarity(const Geom &g, const void *U, int nmu, double *part, double *out, hipStream_t s);
+
 // k_loops.hip -- vortex-only / vortex-removed fields and Wilson loops.
 // A spatial path for the line kernel: n unit steps +-(axis+1), displacement d.
 struct SPathArg {

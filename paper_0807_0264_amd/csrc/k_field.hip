@@ -55,6 +55,16 @@ hipError_t launch_plaquette(const Geom &g, const void *U, double *part, double *
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_unitarity(const Geom &g, const void *U, int nmu, double *part, double *out, hipStream_t s) {
+  const int nb = field_blocks256(g);
+  k_unitarity<T><<<nb, 256, 0, s>>>(g, (const V2<T> *)U, nmu, part);
+  k_max_final<<<1, 256, 0, s>>>(part, nb, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_unitarity<float>(const Geom &, const void *, int, double *, double *, hipStream_t);
+template hipError_t launch_unitarity<double>(const Geom &, const void *, int, double *, double *, hipStream_t);
 template hipError_t launch_pack_links<double, double>(const Geom &, const void *, void *, hipStream_t);
 template hipError_t launch_pack_links<double, float>(const Geom &, const void *, void *, hipStream_t);
 template hipError_t launch_pack_links<float, float>(const Geom &, const void *, void *, hipStream_t);

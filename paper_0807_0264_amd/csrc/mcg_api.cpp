@@ -40,6 +40,9 @@ struct mcg_ctx {
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
+  bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
+  size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
+  size_t scratch_used = 0;
   int stop_every = 1;  // stop test only after sweeps numbered by multiples of this (MCG_OPT_STOP_EVERY)
   int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
 };
@@ -69,8 +72,12 @@ mcg_status fail(mcg_ctx *ctx, mcg_status s, const char *fmt, ...) {
 mcg_status ensure(mcg_ctx *ctx, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return MCG_OK;
+  if (ctx->scratch_limit && ctx->scratch_used - b.cap + bytes > ctx->scratch_limit)
+    return fail(ctx, MCG_ENOMEM, "context scratch limit of %zu bytes reached (%zu held, %zu more requested)",
+                ctx->scratch_limit, ctx->scratch_used, bytes - b.cap);
   if (b.p) {
     hipError_t e = hipFree(b.p);
+    ctx->scratch_used -= b.cap;
     b.p = nullptr;
     b.cap = 0;
     if (e != hipSuccess) return fail(ctx, MCG_EHIP, "hipFree: %s", hipGetErrorString(e));
@@ -81,6 +88,7 @@ mcg_status ensure(mcg_ctx *ctx, DevBuf &b, size_t bytes) {
     return fail(ctx, MCG_ENOMEM, "device allocation of %zu bytes failed", bytes);
   }
   b.cap = bytes;
+  ctx->scratch_used += bytes;
   return MCG_OK;
 }
 
@@ -155,6 +163,45 @@ size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
 }
 
 // ------------------------------------------------------------ fixing driver
+// Largest |(M M^dag - 1)_ij| over U's links (and G's matrices when G is given), NaN as inf; host
+// results, synchronises the stream.
+mcg_status unitarity(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, double *devU, double *devG,
+                     hipStream_t s) {
+  const mcg_dims &d = U ? U->d : G->d;
+  const Geom g = geom_of(d);
+  mcg_status st;
+  if ((st = ensure(ctx, ctx->part, sizeof(double) * field_blocks256(g))) || (st = ensure(ctx, ctx->scalars, 64)))
+    return st;
+  double *dv = (double *)ctx->scalars.p + 4;
+  if (U) {
+    if (U->prec == MCG_F64)
+      HIPCHK(launch_unitarity<double>(g, U->ptr, 4, (double *)ctx->part.p, dv, s));
+    else
+      HIPCHK(launch_unitarity<float>(g, U->ptr, 4, (double *)ctx->part.p, dv, s));
+  }
+  if (G) HIPCHK(launch_unitarity<double>(g, G->ptr, 1, (double *)ctx->part.p, dv + 1, s));
+  double h[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(h, dv, sizeof h, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (devU) *devU = U ? h[0] : 0.0;
+  if (devG) *devG = G ? h[1] : 0.0;
+  return MCG_OK;
+}
+
+// In check mode: MCG_EINPUT unless every link of U (nullable) is unitary to 1e-6 (FP32) or 1e-10
+// (FP64) and every matrix of G (nullable) to 1e-10, with no NaN.
+mcg_status check_inputs(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, hipStream_t s) {
+  if (!ctx->check || (!U && !G)) return MCG_OK;
+  double du = 0.0, dg = 0.0;
+  mcg_status st = unitarity(ctx, U, G, &du, &dg, s);
+  if (st) return st;
+  const double tu = U && U->prec == MCG_F32 ? 1e-6 : 1e-10;
+  if (U && !(du <= tu)) return fail(ctx, MCG_EINPUT, "U is not unitary: max |U U^dag - 1| = %g (limit %g)", du, tu);
+  if (G && !(dg <= 1e-10))
+    return fail(ctx, MCG_EINPUT, "G is not unitary: max |G G^dag - 1| = %g (limit 1e-10)", dg);
+  return MCG_OK;
+}
+
 // Slab plan of a launch table: a field is split into n chunks of its blocks (LatDesc) when every
 // chunk holds at least two time slices' worth of half sites.  Every neighbour of a site then lies
 // in the same chunk or the next one on either side (cyclically): spatial neighbours differ by less
@@ -256,6 +303,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     for (int c = 0; c < b; c++)
       if (U[c].ptr == U[b].ptr && G[c].ptr == G[b].ptr)
         return fail(ctx, MCG_EINVAL, "fields %d and %d share U and G", c, b);
+    if ((st = check_inputs(ctx, &U[b], &G[b], s))) return st;
   }
   const bool c12 = ctx->c12;
   // re-linearisation hits run in one instantiation with 256-thread blocks (variant 2)
@@ -614,6 +662,17 @@ mcg_status mcg_gauge_reunit(mcg_ctx *ctx, mcg_gauge *G, void *stream) {
   return MCG_OK;
 }
 
+mcg_status mcg_unitarity(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, double *dev_U, double *dev_G,
+                         void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if (!U && !G) return fail(ctx, MCG_EINVAL, "U and G are both NULL");
+  if (U && (st = check_field(ctx, U, "U"))) return st;
+  if (G && !U && !dims_valid(G->d)) return fail(ctx, MCG_EINVAL, "G: bad extents");
+  if (G && (st = check_gauge(ctx, G, U ? U->d : G->d, "G"))) return st;
+  return unitarity(ctx, U, G, dev_U, dev_G, (hipStream_t)stream);
+}
+
 mcg_status mcg_smear(mcg_ctx *ctx, const mcg_field *U, mcg_field *out, double rho, double eps, int32_t n,
                      void *stream) {
   if (!ctx) return MCG_EINVAL;
@@ -624,6 +683,7 @@ mcg_status mcg_smear(mcg_ctx *ctx, const mcg_field *U, mcg_field *out, double rh
   if (U->ptr == out->ptr) return fail(ctx, MCG_EINVAL, "U and out must not alias");
   if (n < 0 || std::isnan(rho) || std::isnan(eps)) return fail(ctx, MCG_EINVAL, "bad smearing parameters");
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_inputs(ctx, U, nullptr, s))) return st;
   const size_t bytes = field_bytes(U->d, U->prec);
   if (n == 0) {
     HIPCHK(hipMemcpyAsync(out->ptr, U->ptr, bytes, hipMemcpyDeviceToDevice, s));
@@ -653,6 +713,7 @@ mcg_status mcg_apply_gauge(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G,
     return st;
   if (!same_dims(U->d, out->d) || U->prec != out->prec)
     return fail(ctx, MCG_EINVAL, "U and out differ in extents or precision");
+  if ((st = check_inputs(ctx, U, G, (hipStream_t)stream))) return st;
   const Geom g = geom_of(U->d);
   if (U->prec == MCG_F64)
     HIPCHK(launch_apply_gauge<double>(g, U->ptr, G->ptr, out->ptr, (hipStream_t)stream));
@@ -900,6 +961,16 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->nslab = value;
     return MCG_OK;
   }
+  if (option == MCG_OPT_CHECK) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_CHECK takes 0 or 1");
+    ctx->check = value != 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {
+    if (value < 0) return fail(ctx, MCG_EINVAL, "MCG_OPT_SCRATCH_LIMIT_MIB takes >= 0");
+    ctx->scratch_limit = (size_t)value << 20;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_HITS) {
     if (value < 1 || value > 16) return fail(ctx, MCG_EINVAL, "MCG_OPT_HITS takes 1..16");
     ctx->hits = value;
@@ -926,6 +997,14 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   }
   if (option == MCG_OPT_HITS) {
     *value = ctx->hits;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_CHECK) {
+    *value = ctx->check ? 1 : 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {
+    *value = (int32_t)(ctx->scratch_limit >> 20);
     return MCG_OK;
   }
   if (option == MCG_OPT_STOP_EVERY) {
@@ -971,6 +1050,7 @@ mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge 
   if ((st = check_field(ctx, U, "U"))) return st;
   if (G && (st = check_gauge(ctx, G, U->d, "G"))) return st;
   if (!Z) return fail(ctx, MCG_EINVAL, "Z is NULL");
+  if ((st = check_inputs(ctx, U, G, (hipStream_t)stream))) return st;
   const Geom g = geom_of(U->d);
   if ((st = ensure(ctx, ctx->part, sizeof(double) * field_blocks256(g))) ||
       (st = ensure(ctx, ctx->scalars, 64)))
@@ -1029,6 +1109,7 @@ mcg_status mcg_vortex_field(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G
     return fail(ctx, MCG_EINVAL, "U and out differ in extents or precision");
   if (!Z) return fail(ctx, MCG_EINVAL, "Z is NULL");
   if (mode != MCG_VORTEX_ONLY && mode != MCG_VORTEX_REMOVED) return fail(ctx, MCG_EINVAL, "bad mode %d", mode);
+  if ((st = check_inputs(ctx, U, G, (hipStream_t)stream))) return st;
   const Geom g = geom_of(U->d);
   const double *gp = G ? G->ptr : nullptr;
   hipStream_t s = (hipStream_t)stream;
@@ -1169,6 +1250,7 @@ mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, cons
       return fail(ctx, MCG_EINVAL, "vector %d: rmax * max|v_j| = %lld exceeds the smallest spatial extent %d", i,
                   (long long)rmax * mx, lmin);
   }
+  if ((st = check_inputs(ctx, U, nullptr, (hipStream_t)stream))) return st;
   return U->prec == MCG_F64 ? wilson_impl<double>(ctx, U, nvec, vec, rmax, tmax, W, (hipStream_t)stream)
                             : wilson_impl<float>(ctx, U, nvec, vec, rmax, tmax, W, (hipStream_t)stream);
 }
@@ -1186,6 +1268,7 @@ mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, 
   if (U->ptr == gradU->ptr) return fail(ctx, MCG_EINVAL, "U and gradU must not alias");
   if (n < 0 || std::isnan(rho) || std::isnan(eps)) return fail(ctx, MCG_EINVAL, "bad smearing parameters");
   if (!loss || !dRho || !dEps) return fail(ctx, MCG_EINVAL, "NULL output");
+  if ((st = check_inputs(ctx, U, Gstar, (hipStream_t)stream))) return st;
   return U->prec == MCG_F64
              ? backward_impl<double>(ctx, U, rho, eps, n, Gstar, ckpt_every, gradU, loss, dRho, dEps,
                                      (hipStream_t)stream)

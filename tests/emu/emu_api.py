@@ -265,3 +265,26 @@ def set_variant(prec, v):
 def set_update_variant(hits, stop_every):
     check(lib().mcg_set_option(ctx(), 3, hits))
     check(lib().mcg_set_option(ctx(), 4, stop_every))
+
+
+def set_check(on):
+    check(lib().mcg_set_option(ctx(), 5, 1 if on else 0))
+
+
+def set_scratch_limit_mib(mib):
+    check(lib().mcg_set_option(ctx(), 6, mib))
+
+
+def status_of(fn, *a):
+    """Run a library call that returns a status; give back (status, last error)."""
+    st = fn(*a)
+    return st, lib().mcg_last_error(ctx())
+
+
+def unitarity(U=None, G=None):
+    f = U.abi() if U is not None else None
+    g = G.abi() if G is not None else None
+    du, dg = C.c_double(), C.c_double()
+    check(lib().mcg_unitarity(ctx(), C.byref(f) if f is not None else None, C.byref(g) if g is not None else None,
+                              C.byref(du), C.byref(dg), None))
+    return du.value, dg.value

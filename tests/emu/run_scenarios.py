@@ -223,16 +223,73 @@ def scenario_variants(prec):
     E.set_two_row(True)
 
 
+def expect_error(fn, status_word, what):
+    try:
+        fn()
+    except E.MCGError as e:
+        check(f"(status {status_word})" in str(e), f"{what}: {e}")
+        return str(e)
+    raise AssertionError(f"{what}: no error")
+
+
+def scenario_checks(prec):
+    """Input validation (check mode) and the scratch limit."""
+    L = (4, 4, 4, 4)
+    U = rounded(field(L, 2080), prec)
+    G = S.haar_gauge(L, S.sub_seed(2081))
+    du, dg = E.unitarity(E.links(U, prec), E.gauge(G))
+    check(du < (1e-6 if prec == 1 else 1e-13) and dg < 1e-13, f"unitary inputs {du} {dg}")
+    bad = U.copy()
+    bad[1, 2, 3, 0, 2] *= 1.001
+    check(abs(E.unitarity(E.links(bad, prec))[0] - 0.002001) < 1e-4, "deviation of a scaled link")
+    nan = U.copy()
+    nan[0, 0, 0, 1, 3, 1, 2] = np.nan
+    check(E.unitarity(E.links(nan, prec))[0] == np.inf, "NaN reads as inf")
+    Gbad = G.copy()
+    Gbad[0, 1, 0, 0] *= 1 + 1e-8
+    check(E.unitarity(None, E.gauge(Gbad))[1] > 1e-9, "perturbed G")
+    E.set_check(True)
+    try:
+        for Ub in (bad, nan):
+            msg = expect_error(lambda: E.smear(E.links(Ub, prec), 0.1, 1.0, 1), -4, "smear")
+            check("not unitary" in msg, msg)
+            expect_error(lambda: E.fix(E.links(Ub, prec), None, tol=-1.0, max_sweeps=2), -4, "fix")
+        expect_error(lambda: E.fix(E.links(U, prec), E.gauge(Gbad), tol=-1.0, max_sweeps=2), -4, "fix G")
+        expect_error(lambda: E.apply_gauge(E.links(U, prec), E.gauge(Gbad)), -4, "apply_gauge")
+        expect_error(lambda: E.center_project(E.links(bad, prec), None), -4, "center_project")
+        expect_error(lambda: E.wilson_loops(E.links(bad, prec), [(1, 0, 0)], 1, 1), -4, "wilson_loops")
+        # valid inputs pass in check mode and give the unchecked results
+        a = E.host_links(E.smear(E.links(U, prec), 0.1, 1.0, 2))
+    finally:
+        E.set_check(False)
+    check(np.array_equal(a, E.host_links(E.smear(E.links(U, prec), 0.1, 1.0, 2))), "check mode changes nothing")
+    check(E.host_links(E.smear(E.links(bad, prec), 0.1, 1.0, 1)).shape == U.shape, "unchecked call runs")
+    # the scratch limit: a fix of this size needs a larger working field than any before it (>1 MiB)
+    L8 = (8, 8, 8, 8) if prec == 0 else (12, 12, 8, 8)
+    U8 = rounded(field(L8, 2082, 1), prec)
+    E.set_scratch_limit_mib(1)
+    try:
+        msg = expect_error(lambda: E.fix(E.links(U8, prec), None, tol=-1.0, max_sweeps=1), -2, "scratch limit")
+        check("scratch limit" in msg, msg)
+    finally:
+        E.set_scratch_limit_mib(0)
+    _, info = E.fix(E.links(U8, prec), None, tol=-1.0, max_sweeps=1)
+    check(info["sweeps"] == 1, "usable after the limit")
+
+
 def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
     names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward",
-                             "loops", "slabs", "variants"]
+                             "loops", "slabs", "variants", "checks"]
     for name in names:
         if name == "batch":
             for prec in (0, 1):
                 scenario_batch(prec)
         elif name == "planted":
             scenario_planted()
+        elif name == "checks":
+            for prec in (0, 1):
+                scenario_checks(prec)
         elif name == "variants":
             for prec in (0, 1):
                 scenario_variants(prec)

@@ -1,0 +1,97 @@
+"""Input validation on the GPU: the unitarity deviation against numpy, the
+check mode's MCG_EINPUT on non-unitary or NaN links and transforms, and the
+context's scratch limit (MCG_ENOMEM, context still usable)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import gpu_util
+    return gpu_util
+
+
+def deviation(M):
+    M = M.reshape(-1, 3, 3)
+    return np.abs(M @ np.conj(np.swapaxes(M, -1, -2)) - np.eye(3)).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_unitarity_and_check_mode(S, g, prec):
+    from paper_0807_0264_amd import api
+    from paper_0807_0264_amd.api import MCGError
+    L = (6, 4, 4, 8)
+    U = g.rounded(S.heatbath_field(L, S.sub_seed(7000), 5.7, 3), prec)
+    G = S.haar_gauge(L, S.sub_seed(7001))
+    du, dg = api.unitarity(g.links(U, prec), g.gauge(G))
+    assert du < (1e-6 if prec == 1 else 1e-13) and dg < 1e-13
+    bad = U.copy()
+    bad[3, 1, 2, 5, 1] *= 1.0005
+    bad = g.rounded(bad, prec)
+    # the deviation of the complex entries as numpy computes it (max over real and imaginary parts)
+    M = bad.reshape(-1, 3, 3)
+    P = M @ np.conj(np.swapaxes(M, -1, -2)) - np.eye(3)
+    want = max(np.abs(P.real).max(), np.abs(P.imag).max())
+    assert abs(api.unitarity(g.links(bad, prec))[0] - want) < 1e-6 * want + (1e-7 if prec else 1e-14)
+    nan = U.copy()
+    nan[0, 0, 1, 0, 2, 0, 0] = np.nan
+    assert api.unitarity(g.links(nan, prec))[0] == np.inf
+    Gbad = G.copy()
+    Gbad[1, 0, 0, 0] *= 1 + 1e-8
+    assert api.unitarity(None, g.gauge(Gbad))[1] > 1e-9
+    api.set_check(True)
+    try:
+        for Ub in (bad, nan):
+            with pytest.raises(MCGError, match="not unitary"):
+                api.smear(g.links(Ub, prec), 0.1, 1.0, 1)
+            with pytest.raises(MCGError, match="not unitary"):
+                api.fix(g.links(Ub, prec), None, tol=-1.0, max_sweeps=2)
+            with pytest.raises(MCGError, match="not unitary"):
+                api.center_project(g.links(Ub, prec), None)
+        with pytest.raises(MCGError, match="G is not unitary"):
+            api.fix(g.links(U, prec), g.gauge(Gbad), tol=-1.0, max_sweeps=2)
+        with pytest.raises(MCGError, match="G is not unitary"):
+            api.apply_gauge(g.links(U, prec), g.gauge(Gbad))
+        with pytest.raises(MCGError, match="not unitary"):
+            api.wilson_loops(g.links(bad, prec), [(1, 0, 0)], 1, 1)
+        a = g.host_links(api.smear(g.links(U, prec), 0.1, 1.0, 2))
+        _, info = api.fix(g.links(U, prec), g.gauge(G), tol=-1.0, max_sweeps=3, want_traj=True)
+    finally:
+        api.set_check(False)
+    assert np.array_equal(a, g.host_links(api.smear(g.links(U, prec), 0.1, 1.0, 2)))
+    _, info2 = api.fix(g.links(U, prec), g.gauge(G), tol=-1.0, max_sweeps=3, want_traj=True)
+    assert np.array_equal(info["traj"], info2["traj"])
+
+
+def test_scratch_limit(S, g):
+    """A fresh context (the shared one may already hold large buffers) with a
+    4 MiB scratch cap: a fix needing a ~38 MB working field returns
+    MCG_ENOMEM and the same context then works once the cap is lifted."""
+    import ctypes as C
+
+    import torch
+    from paper_0807_0264_amd import _abi as A
+    from paper_0807_0264_amd import api
+    lib = A.load()
+    L = (16, 16, 16, 32)
+    U = api.to_links(S.haar_links_gpu(L, 11), 1)
+    G = api.gauge_identity(L)
+    ctx = C.c_void_p()
+    assert lib.mcg_create(C.byref(ctx), torch.cuda.current_device()) == A.MCG_OK
+    try:
+        assert lib.mcg_set_option(ctx, A.MCG_OPT_SCRATCH_LIMIT_MIB, 4) == A.MCG_OK
+        o = api._opts(-1.0, 1, 1.7, 50, 0, 50, None)
+        r = A.FixResult()
+        f, gg = U.abi(), G.abi()
+        st = lib.mcg_fix(ctx, C.byref(f), C.byref(gg), C.byref(o), C.byref(r), api._stream())
+        assert st == A.MCG_ENOMEM and b"scratch limit" in lib.mcg_last_error(ctx)
+        assert lib.mcg_set_option(ctx, A.MCG_OPT_SCRATCH_LIMIT_MIB, 0) == A.MCG_OK
+        st = lib.mcg_fix(ctx, C.byref(f), C.byref(gg), C.byref(o), C.byref(r), api._stream())
+        assert st == A.MCG_WNOTCONV and r.sweeps == 1
+    finally:
+        assert lib.mcg_destroy(ctx) == A.MCG_OK
