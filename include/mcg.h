@@ -10,7 +10,9 @@
  *   count_vortices(Z)            Sec. II.A (non-trivial plaquettes of Z)
  *
  * Conventions
- *   - Extents L = (Lx, Ly, Lz, Lt), each even and >= 2, periodic; site index
+ *   - Extents L = (Lx, Ly, Lz, Lt), each even and >= 2, with at most
+ *     53,687,091 sites (80 V < 2^32: device loads use 32-bit byte offsets
+ *     within a field), else MCG_EINVAL; periodic; site index
  *     i = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2; half index
  *     h = i >> 1 (the site's index among the V/2 sites of its parity).
  *   - Gauge transform: U^G_mu(x) = G(x) U_mu(x) G(x+mu)^dagger.

@@ -75,7 +75,7 @@ class Links:
         need = A.load().mcg_field_bytes(_dims(self.L), self.prec)
         have = self.data.numel() * self.data.element_size()
         if need == 0:
-            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2")
+            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2, with fewer than 53,687,092 sites")
         if have < need:
             raise ValueError(f"link buffer of {have} bytes, the field needs {need}")
         f = A.Field()
@@ -101,7 +101,7 @@ class GaugeField:
         need = A.load().mcg_gauge_bytes(_dims(self.L))
         have = self.data.numel() * self.data.element_size()
         if need == 0:
-            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2")
+            raise ValueError(f"invalid extents {self.L}: each must be even and >= 2, with fewer than 53,687,092 sites")
         if have < need:
             raise ValueError(f"gauge buffer of {have} bytes, the field needs {need}")
         g = A.Gauge()
@@ -127,7 +127,7 @@ def empty_links(L, prec, device=None):
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
     nbytes = A.load().mcg_field_bytes(_dims(L), prec)
     if nbytes == 0:
-        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2")
+        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2, with fewer than 53,687,092 sites")
     return Links(tuple(int(v) for v in L), prec,
                  torch.empty(nbytes // torch.empty((), dtype=dt).element_size(), dtype=dt, device=dev))
 
@@ -136,7 +136,7 @@ def empty_gauge(L, device=None):
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
     nbytes = A.load().mcg_gauge_bytes(_dims(L))
     if nbytes == 0:
-        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2")
+        raise ValueError(f"invalid extents {tuple(L)}: each must be even and >= 2, with fewer than 53,687,092 sites")
     return GaugeField(tuple(int(v) for v in L), torch.empty(nbytes // 8, dtype=torch.float64, device=dev))
 
 

@@ -111,8 +111,9 @@ bool dims_valid(const mcg_dims &d) {
     if (d.L[k] < 2 || (d.L[k] & 1)) return false;
     V *= d.L[k];
   }
-  // 32-bit site indices; 72 complex planes of V/2 must fit in 31 bits
-  return V <= (int64_t(1) << 30) && 72 * (V / 2) < (int64_t(1) << 31);
+  // Loads address a (mu, k) plane by a wave-uniform base pointer plus a 32-bit byte offset of up to
+  // (9 V/2 + V/2) * 16 = 80 V (FP64 elements, both parities), so 80 V < 2^32: V < 53,687,092.
+  return 80 * V < (int64_t(1) << 32);
 }
 
 Geom geom_of(const mcg_dims &d) {
@@ -131,7 +132,7 @@ bool same_dims(const mcg_dims &a, const mcg_dims &b) {
 mcg_status check_field(mcg_ctx *ctx, const mcg_field *f, const char *name) {
   if (!f) return fail(ctx, MCG_EINVAL, "%s is NULL", name);
   if (!dims_valid(f->d))
-    return fail(ctx, MCG_EINVAL, "%s: extents (%d,%d,%d,%d) must be even, >= 2, V <= 2^30", name,
+    return fail(ctx, MCG_EINVAL, "%s: extents (%d,%d,%d,%d) must be even, >= 2, with V < 53687092", name,
                 f->d.L[0], f->d.L[1], f->d.L[2], f->d.L[3]);
   if (f->prec != MCG_F64 && f->prec != MCG_F32) return fail(ctx, MCG_EINVAL, "%s: bad precision %d", name, f->prec);
   if (!f->ptr) return fail(ctx, MCG_EINVAL, "%s: NULL data pointer", name);

@@ -60,3 +60,9 @@ def test_buffer_sizes():
     assert lib.mcg_gauge_bytes(d) == V * 9 * 2 * 8
     d.L[1] = 5
     assert lib.mcg_field_bytes(d, _abi.MCG_F64) == 0 and lib.mcg_gauge_bytes(d) == 0
+    # the largest lattices: 80 V < 2^32 (32-bit byte offsets of FP64 elements)
+    for k, v in enumerate((64, 64, 64, 204)):
+        d.L[k] = v
+    assert lib.mcg_gauge_bytes(d) == 64 ** 3 * 204 * 9 * 16
+    d.L[3] = 206
+    assert lib.mcg_field_bytes(d, _abi.MCG_F32) == 0 and lib.mcg_gauge_bytes(d) == 0
