@@ -384,6 +384,15 @@ template <typename T> struct FixStore<T, true> {
 };
 
 // ------------------------------------------------------------- reductions
+// Butterfly sum over the 64 lanes of a wavefront (result in every lane): the
+// same tree whatever the block size, so per-wave partials written at the
+// wave's global index make a reduction independent of the launch shape.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // Deterministic block sum of one double per thread: butterfly within each
 // 64-wide wavefront, then the per-wave sums in wave order.  Result valid in
 // thread 0.  BS must be a multiple of 64.

@@ -43,7 +43,8 @@ template <typename T> struct LatDesc {
   const V2<T> *U;  // the field being fixed (read only)
   double2 *G;      // gauge transform (FP64)
   FixState *st;
-  double *part;    // nblk partial sums
+  double *part;    // npart = nblk * BS / 64 partial sums, one per 64-site wavefront
+  int npart;
   double *traj;    // device copy of the R trajectory (max_k + 1) or null
 };
 

@@ -327,7 +327,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     const int nb = nblocks(g, bs);
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12)))) return st;
     if (c12 && (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, true)))) return st;
-    if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb))) return st;
+    if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb * (bs / 64)))) return st;
     const bool want_traj = opts[b].traj != nullptr;
     if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
     LatDesc<T> d;
@@ -339,6 +339,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     d.G = c12 ? (double2 *)ctx->G12[b].p : (double2 *)G[b].ptr;
     d.st = (FixState *)ctx->states.p + b;
     d.part = (double *)ctx->fpart[b].p;
+    d.npart = nb * (bs / 64);
     d.traj = want_traj ? (double *)ctx->traj[b].p : nullptr;
     hD[b] = d;
     FixState f;

@@ -203,8 +203,8 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
     G.store(par, h, mul(m_cvt<double>(g), G.load(par, h)));
   }
   if (WR) {
-    const double s = block_sum<BS>(r);
-    if (threadIdx.x == 0) d.part[lb] = s;
+    const double s = wave_sum(r);
+    if ((threadIdx.x & 63) == 0) d.part[lb * (BS / 64) + (threadIdx.x >> 6)] = s;
   }
 }
 
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ 
       }
     }
   }
-  const double s = block_sum<BS>(r);
-  if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+  const double s = wave_sum(r);
+  if ((threadIdx.x & 63) == 0) d.part[((int)blockIdx.x - d.blk0) * (BS / 64) + (threadIdx.x >> 6)] = s;
 }
 
 template <typename T, int BS, bool C12>
@@ -287,8 +287,8 @@ __global__ __launch_bounds__(BS) void k_theta(const LatDesc<T> *__restrict__ D, 
       r += (double)rdot(t, t);
     }
   }
-  const double s = block_sum<BS>(r);
-  if (threadIdx.x == 0) d.part[blockIdx.x - d.blk0] = s;
+  const double s = wave_sum(r);
+  if ((threadIdx.x & 63) == 0) d.part[((int)blockIdx.x - d.blk0) * (BS / 64) + (threadIdx.x >> 6)] = s;
 }
 
 // Conversion between the full and the two-row forms (to12: full -> rows;
@@ -322,7 +322,8 @@ __global__ __launch_bounds__(256) void k_gauge_form(Geom g, const double2 *__res
 }
 
 // ------------------------------------------------------ bookkeeping
-// One block per field (grid = B).  R is normalised as (1/(9 N_l)) sum |tr|^2.
+// One block per field (grid = B).  R is normalised as (1/(9 N_l)) sum |tr|^2, summed
+// over the per-wavefront partials in index order (independent of the block size).
 enum { BK_INIT = 0, BK_RESET = 1, BK_CHECK = 2, BK_FINAL = 3, BK_THETA = 4 };
 
 template <typename T>
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
   const LatDesc<T> d = D[blockIdx.x];
   FixState *st = d.st;
   if ((what == BK_RESET || what == BK_CHECK) && st->done) return;
-  const double s = sum_partials<256>(d.part, d.nblk);
+  const double s = sum_partials<256>(d.part, d.npart);
   if (threadIdx.x != 0) return;
   const double R = s / (9.0 * (double)(4 * d.g.V));
   switch (what) {

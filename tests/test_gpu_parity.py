@@ -363,3 +363,29 @@ def test_update_variants(S, O, g, api, L, prec):
     finally:
         api.set_update_variant(1, 1)
         api.set_two_row(True)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fix_is_bitwise_across_launch_variants(S, g, api, prec):
+    """The FP64 partial sums of R are per 64-site wavefront in index order, so
+    the block size and occupancy of the launch do not change any bit of the
+    trajectory, the stop sweep or the transform."""
+    L = (6, 6, 6, 10)
+    U = g.rounded(field(S, L, 1070), prec)
+    ref = None
+    try:
+        for two_row in (True, False):
+            api.set_two_row(two_row)
+            for v in range(6):
+                api.set_variant(prec, v)
+                G, info = api.fix(g.links(U, prec), None, tol=1e-6, max_sweeps=120, reunit_every=25,
+                                  check_every=10, want_traj=True)
+                got = (g.host_gauge(G), info["traj"], info["sweeps"])
+                if ref is None or ref[0] != two_row:
+                    ref = (two_row, got)
+                else:
+                    assert np.array_equal(got[0], ref[1][0]) and np.array_equal(got[1], ref[1][1]), v
+                    assert got[2] == ref[1][2]
+    finally:
+        api.set_two_row(True)
+        api.set_variant(prec, 2)
