@@ -63,14 +63,15 @@ def make_inputs(api, synth, torch):
     return fields
 
 
-def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-7, max_sweeps=5000,
+def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6, max_sweeps=5000,
                   r_match=1e-6):
     """Gribov copies of one field: Haar-random start transforms g_c, each copy
     fixed without smearing and with nsmear stout steps (then carried back and
     re-fixed), centre-projected and vortex-counted.  Every level runs once with
     all copies batched in FP32 links and once copy by copy with FP64 links
     (the same FP32-rounded input); a copy counts as matched when its two final
-    R agree to r_match.  Rounding differences steer a copy to a different
+    R agree to r_match; both paths stop on the same criterion dR < tol = 1e-6.
+    Rounding differences steer a copy to a different
     local maximum after enough over-relaxed sweeps, so the R distributions of
     the two precisions are compared too (means, standard errors, Welch t), and
     the sweep at which each copy's two R trajectories first differ by more

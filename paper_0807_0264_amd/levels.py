@@ -30,6 +30,8 @@ class Level:
 # the preconditioning levels of Sec. III: stout rho = 0.1 with 0..20 steps in
 # steps of 4, and 80 over-improved steps with rho = 0.06, eps = -0.25
 PAPER_LEVELS = tuple([Level(str(n), 0.1, 1.0, n) for n in range(0, 21, 4)] + [Level("OI 80", 0.06, -0.25, 80)])
+# a wider range of stout steps (0, 10, 50, 100 at rho = 0.1) against the same over-improved level
+WIDE_LEVELS = tuple([Level(str(n), 0.1, 1.0, n) for n in (0, 10, 50, 100)] + [Level("OI 80", 0.06, -0.25, 80)])
 
 
 def run_levels(U, levels=PAPER_LEVELS, G0=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50,
@@ -186,6 +188,8 @@ def main(argv=None):
     ap.add_argument("--beta", type=float, default=5.7)
     ap.add_argument("--prec", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--levels", choices=("paper", "wide"), default="paper",
+                    help="paper: stout 0..20 in steps of 4 and OI 80; wide: stout 0, 10, 50, 100 and OI 80")
     ap.add_argument("--compare", action="store_true",
                     help="run every configuration in both precisions and report the FP32 - FP64 differences")
     ap.add_argument("--json", action="store_true", help="print the raw per-configuration results as JSON")
@@ -199,7 +203,8 @@ def main(argv=None):
         if a.compare:
             U64 = U64.to(torch.complex64).to(torch.complex128)
         for p in precs:
-            results[p].append(run_levels(api.to_links(U64, p), tol=a.tol))
+            levels = PAPER_LEVELS if a.levels == "paper" else WIDE_LEVELS
+            results[p].append(run_levels(api.to_links(U64, p), levels, tol=a.tol))
         torch.cuda.synchronize()
         print(f"configuration {c}: " + ", ".join(f"{r['level']}: R {r['R']:.5f} v {r['vortices']}"
                                                  for r in results[precs[0]][-1]), flush=True)
