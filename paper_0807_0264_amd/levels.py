@@ -174,8 +174,9 @@ def format_tables(results):
 
 
 def main(argv=None):
-    """Synthetic stand-in for the paper's study: configurations from the
-    seeded Wilson heatbath, all preconditioning levels per configuration."""
+    """Synthetic stand-in for the paper's study: configurations from a seeded
+    heatbath (Wilson, or the Luscher-Weisz action of the paper's ensemble),
+    all preconditioning levels per configuration."""
     import argparse
     import json
 
@@ -185,7 +186,11 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--configs", type=int, default=8)
     ap.add_argument("--lattice", default="20,20,20,40")
-    ap.add_argument("--beta", type=float, default=5.7)
+    ap.add_argument("--action", choices=("wilson", "lw"), default="wilson",
+                    help="input fields: Wilson heatbath, or Luscher-Weisz (plaquette + rectangle) heatbath")
+    ap.add_argument("--beta", type=float, default=None, help="coupling (default 5.7 Wilson, 4.52 Luscher-Weisz)")
+    ap.add_argument("--u0", type=float, default=0.884, help="tadpole factor of the Luscher-Weisz rectangle weight")
+    ap.add_argument("--therm", type=int, default=None, help="heatbath sweeps from the Haar start (50 / 100)")
     ap.add_argument("--prec", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--levels", choices=("paper", "wide"), default="paper",
@@ -197,8 +202,14 @@ def main(argv=None):
     L = tuple(int(v) for v in a.lattice.split(","))
     precs = (1, 0) if a.compare else ((1,) if a.prec == "fp32" else (0,))
     results = {p: [] for p in precs}
+    lw = a.action == "lw"
+    beta = a.beta if a.beta is not None else (4.52 if lw else 5.7)
+    therm = a.therm if a.therm is not None else (100 if lw else 50)
     for c in range(a.configs):
-        U64 = synth.heatbath_field_gpu(L, synth.sub_seed(11, c), a.beta, 50)
+        if lw:
+            U64 = synth.heatbath_lw_field_gpu(L, synth.sub_seed(12, c), beta, therm, a.u0)
+        else:
+            U64 = synth.heatbath_field_gpu(L, synth.sub_seed(11, c), beta, therm)
         # both precisions start from the same (FP32-rounded when comparing) values
         if a.compare:
             U64 = U64.to(torch.complex64).to(torch.complex128)

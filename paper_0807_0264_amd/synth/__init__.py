@@ -65,6 +65,10 @@ def cpu():
         l.sy_cpu_z3.argtypes = [I4, C.c_uint64, P]
         l.sy_cpu_gauss.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, P]
         l.sy_cpu_heatbath.argtypes = [I4, C.c_uint64, C.c_double, C.c_int, P]
+        l.sy_cpu_heatbath_lw.argtypes = [I4, C.c_uint64, C.c_double, C.c_double, C.c_int, P]
+        l.sy_cpu_lw_staple.argtypes = [I4, P, C.c_int64, C.c_int, C.c_double, C.c_double, P]
+        l.sy_cpu_lw_colour.argtypes = [I4, C.c_int64, C.c_int]
+        l.sy_cpu_lw_colour.restype = C.c_int
         for f in ("sy_cpu_log", "sy_cpu_sqrt", "sy_cpu_recip"):
             getattr(l, f).argtypes = [C.c_double]
             getattr(l, f).restype = C.c_double
@@ -83,7 +87,8 @@ def gpu():
         l.sy_gpu_haar_links.argtypes = [I4, C.c_uint64, P, P]
         l.sy_gpu_haar_gauge.argtypes = [I4, C.c_uint64, C.c_uint64, P, P]
         l.sy_gpu_heatbath.argtypes = [I4, C.c_uint64, C.c_double, C.c_int, P, P]
-        for f in ("sy_gpu_haar_links", "sy_gpu_haar_gauge", "sy_gpu_heatbath"):
+        l.sy_gpu_heatbath_lw.argtypes = [I4, C.c_uint64, C.c_double, C.c_double, C.c_int, P, P]
+        for f in ("sy_gpu_haar_links", "sy_gpu_haar_gauge", "sy_gpu_heatbath", "sy_gpu_heatbath_lw"):
             getattr(l, f).restype = C.c_int
         _gpu = l
     return _gpu
@@ -139,6 +144,20 @@ def heatbath_field(L, seed, beta=5.7, nsweeps=50):
     return out
 
 
+def _check_lw(L):
+    if any(int(v) % 4 for v in L):
+        raise ValueError(f"Luscher-Weisz heatbath needs extents divisible by 4, got {tuple(L)}")
+
+
+def heatbath_lw_field(L, seed, beta=4.52, nsweeps=50, u0=1.0):
+    """Haar start, then nsweeps heatbath sweeps of the Luscher-Weisz action
+    (plaquette weight 5/3, rectangle weight -1/(12 u0^2))."""
+    _check_lw(L)
+    out = np.empty(link_shape(L), np.complex128)
+    cpu().sy_cpu_heatbath_lw(_I4(L), seed, beta, float(u0), int(nsweeps), out.ctypes.data_as(C.c_void_p))
+    return out
+
+
 # ---- gfx950 generator (torch tensors on the GPU; bit-identical output) --------------
 def _stream_ptr(stream):
     import torch
@@ -153,6 +172,17 @@ def heatbath_field_gpu(L, seed, beta=5.7, nsweeps=50, device="cuda", stream=None
                                _stream_ptr(stream))
     if rc != 0:
         raise RuntimeError(f"sy_gpu_heatbath failed with HIP error {rc}")
+    return out
+
+
+def heatbath_lw_field_gpu(L, seed, beta=4.52, nsweeps=50, u0=1.0, device="cuda", stream=None):
+    import torch
+    _check_lw(L)
+    out = torch.empty(link_shape(L), dtype=torch.complex128, device=device)
+    rc = gpu().sy_gpu_heatbath_lw(_I4(L), seed, beta, float(u0), int(nsweeps), C.c_void_p(out.data_ptr()),
+                                  _stream_ptr(stream))
+    if rc != 0:
+        raise RuntimeError(f"sy_gpu_heatbath_lw failed with HIP error {rc}")
     return out
 
 

@@ -284,11 +284,85 @@ SY_FN void sy_wilson_staple(const sy_lat *lt, const double *U, int64_t x,
  * subgroup (0,1),(1,2),(0,2) a left factor s is drawn from
  * exp((beta/3) Re tr(s w)) with w the 2x2 block of U A; the Kennedy-Pendleton
  * algorithm samples the quaternion component X0. */
+SY_FN void sy_heatbath_update(const sy_lat *lt, const double *U, int64_t x,
+                              int mu, double beta, uint64_t key, int sweep,
+                              const sy_c A[9], sy_c u[9]);
 SY_FN void sy_heatbath_link(const sy_lat *lt, const double *U, int64_t x,
                             int mu, double beta, uint64_t key, int sweep,
                             sy_c u[9]) {
   sy_c A[9];
   sy_wilson_staple(lt, U, x, mu, A);
+  sy_heatbath_update(lt, U, x, mu, beta, key, sweep, A, u);
+}
+
+/* ---- Luscher-Weisz (plaquette + rectangle) action ------------------------
+ * S = beta sum_P c0 (1 - Re tr P / 3) + beta sum_R c1 (1 - Re tr R / 3),
+ * c0 = 5/3, c1 = -1/(12 u0^2) (u0 = 1: tree level).  Its dependence on
+ * U_mu(x) is (beta/3) Re tr(U_mu(x) A) with A = c0 (6 plaquette staples) +
+ * c1 (18 rectangle staples). */
+
+/* product of the links along `steps` (+-(d+1)) from site y */
+SY_FN void sy_walk(const sy_lat *lt, const double *U, int64_t y, const int *steps, int n, sy_c P[9]) {
+  sy_c a[9], t[9];
+  for (int k = 0; k < 9; k++) { P[k].re = (k % 4 == 0) ? 1.0 : 0.0; P[k].im = 0.0; }
+  for (int q = 0; q < n; q++) {
+    int d = (steps[q] > 0 ? steps[q] : -steps[q]) - 1;
+    if (steps[q] > 0) {
+      sy_load(U + (y * 4 + d) * 18, a);
+      sy_mm(P, a, t);
+      y = sy_shift(lt, y, d, 1);
+    } else {
+      y = sy_shift(lt, y, d, -1);
+      sy_load(U + (y * 4 + d) * 18, a);
+      sy_mmd(P, a, t);
+    }
+    for (int k = 0; k < 9; k++) P[k] = t[k];
+  }
+}
+
+SY_FN void sy_lw_staple(const sy_lat *lt, const double *U, int64_t x, int mu, double c0, double c1,
+                        sy_c A[9]) {
+  for (int k = 0; k < 9; k++) { A[k].re = 0.0; A[k].im = 0.0; }
+  const int64_t xpm = sy_shift(lt, x, mu, 1);
+  const int M = mu + 1;
+  for (int nu = 0; nu < 4; nu++) {
+    if (nu == mu) continue;
+    for (int sg = 1; sg >= -1; sg -= 2) {
+      const int N = sg * (nu + 1);
+      /* closing paths from x + mu back to x: plaquette, then the rectangles
+       * 2x1 ahead, 2x1 behind (long in mu) and 1x2 (long in nu) */
+      const int pl[3] = {N, -M, -N};
+      const int r1[5] = {M, N, -M, -M, -N};
+      const int r2[5] = {N, -M, -M, -N, M};
+      const int r3[5] = {N, N, -M, -N, -N};
+      sy_c P[9];
+      sy_walk(lt, U, xpm, pl, 3, P);
+      for (int k = 0; k < 9; k++) { A[k].re = A[k].re + c0 * P[k].re; A[k].im = A[k].im + c0 * P[k].im; }
+      const int *rs[3] = {r1, r2, r3};
+      for (int r = 0; r < 3; r++) {
+        sy_walk(lt, U, xpm, rs[r], 5, P);
+        for (int k = 0; k < 9; k++) { A[k].re = A[k].re + c1 * P[k].re; A[k].im = A[k].im + c1 * P[k].im; }
+      }
+    }
+  }
+}
+
+/* Update colour of link (x, mu), 0..7: (x_mu mod 2) + 2 ((sum of the other
+ * coordinates) mod 4).  Two links of direction mu in a common plaquette or
+ * rectangle are displaced by +-nu, +-2 nu or +-mu +-nu (nu != mu) and so get
+ * different colours (extents divisible by 4), so all links of one colour can
+ * be updated at once. */
+SY_FN int sy_lw_colour(const sy_lat *lt, int64_t i, int mu) {
+  int64_t c[4], r = i, s = 0;
+  for (int k = 0; k < 4; k++) { c[k] = r % lt->L[k]; r = r / lt->L[k]; }
+  for (int k = 0; k < 4; k++)
+    if (k != mu) s += c[k];
+  return (int)(c[mu] & 1) + 2 * (int)(s & 3);
+}
+
+SY_FN void sy_heatbath_update(const sy_lat *lt, const double *U, int64_t x,
+                              int mu, double beta, uint64_t key, int sweep,
+                              const sy_c A[9], sy_c u[9]) {
   sy_load(U + (x * 4 + mu) * 18, u);
   const int SI[3] = {0, 1, 0}, SJ[3] = {1, 2, 2};
   for (int q = 0; q < 3; q++) {
@@ -366,5 +440,6 @@ SY_FN void sy_heatbath_link(const sy_lat *lt, const double *U, int64_t x,
 #define SY_P_HAAR_GAUGE 3
 #define SY_P_Z3 4
 #define SY_P_GAUSS 5
+#define SY_P_HEATBATH_LW 6
 
 #endif

@@ -89,6 +89,50 @@ void sy_cpu_heatbath(const int32_t L[4], uint64_t seed, double beta, int nsweeps
   }
 }
 
+/* Haar start, then nsweeps Cabibbo-Marinari heatbath sweeps of the
+ * Luscher-Weisz action (c0 = 5/3, c1 = -1/(12 u0^2)) at coupling beta.  A
+ * sweep visits mu = 0..3 and, within each mu, the eight link colours in turn
+ * (sy_lw_colour); every extent must be divisible by 4.  Links are
+ * re-unitarised after every sweep. */
+void sy_cpu_heatbath_lw(const int32_t L[4], uint64_t seed, double beta, double u0, int nsweeps, double *U) {
+  sy_lat lt = mk(L);
+  sy_cpu_haar_links(L, seed, U);
+  uint64_t key = sy_key(seed, SY_P_HEATBATH_LW);
+  const double c0 = 5.0 / 3.0, c1 = -sy_recip(12.0 * u0 * u0);
+  for (int sw = 0; sw < nsweeps; sw++) {
+    for (int mu = 0; mu < 4; mu++)
+      for (int col = 0; col < 8; col++) {
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < lt.V; x++) {
+          if (sy_lw_colour(&lt, x, mu) != col) continue;
+          sy_c A[9], u[9];
+          sy_lw_staple(&lt, U, x, mu, c0, c1, A);
+          sy_heatbath_update(&lt, U, x, mu, beta, key, sw, A, u);
+          sy_store(U + (x * 4 + mu) * 18, u);
+        }
+      }
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < 4 * lt.V; l++) {
+      sy_c m[9];
+      sy_load(U + l * 18, m);
+      sy_reunit(m);
+      sy_store(U + l * 18, m);
+    }
+  }
+}
+
+/* the Luscher-Weisz staple and the update colour, exported for their tests */
+void sy_cpu_lw_staple(const int32_t L[4], const double *U, int64_t x, int mu, double c0, double c1, double *A) {
+  sy_lat lt = mk(L);
+  sy_c a[9];
+  sy_lw_staple(&lt, U, x, mu, c0, c1, a);
+  sy_store(A, a);
+}
+int sy_cpu_lw_colour(const int32_t L[4], int64_t x, int mu) {
+  sy_lat lt = mk(L);
+  return sy_lw_colour(&lt, x, mu);
+}
+
 /* the generator's own elementary functions, exported for their tests */
 double sy_cpu_log(double x) { return sy_log(x); }
 double sy_cpu_sqrt(double x) { return sy_sqrt(x); }

@@ -34,6 +34,16 @@ __global__ void k_sy_heatbath(sy_lat lt, double *U, int mu, int par, double beta
   sy_store(U + (x * 4 + mu) * 18, u);
 }
 
+__global__ void k_sy_heatbath_lw(sy_lat lt, double *U, int mu, int col, double beta, double c0, double c1,
+                                 uint64_t key, int sweep) {
+  int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= lt.V || sy_lw_colour(&lt, x, mu) != col) return;
+  sy_c A[9], u[9];
+  sy_lw_staple(&lt, U, x, mu, c0, c1, A);
+  sy_heatbath_update(&lt, U, x, mu, beta, key, sweep, A, u);
+  sy_store(U + (x * 4 + mu) * 18, u);
+}
+
 __global__ void k_sy_reunit(int64_t n, double *U) {
   int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= n) return;
@@ -75,6 +85,23 @@ int sy_gpu_heatbath(const int32_t L[4], uint64_t seed, double beta, int nsweeps,
     for (int mu = 0; mu < 4; mu++)
       for (int par = 0; par < 2; par++)
         k_sy_heatbath<<<blocks(lt.V / 2, 128), 128, 0, s>>>(lt, U, mu, par, beta, key, sw);
+    k_sy_reunit<<<blocks(4 * lt.V, 256), 256, 0, s>>>(4 * lt.V, U);
+  }
+  return (int)hipGetLastError();
+}
+
+int sy_gpu_heatbath_lw(const int32_t L[4], uint64_t seed, double beta, double u0, int nsweeps, double *U,
+                       void *stream) {
+  sy_lat lt = mk(L);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = sy_gpu_haar_links(L, seed, U, stream);
+  if (rc) return rc;
+  uint64_t key = sy_key(seed, SY_P_HEATBATH_LW);
+  const double c0 = 5.0 / 3.0, c1 = -sy_recip(12.0 * u0 * u0);
+  for (int sw = 0; sw < nsweeps; sw++) {
+    for (int mu = 0; mu < 4; mu++)
+      for (int col = 0; col < 8; col++)
+        k_sy_heatbath_lw<<<blocks(lt.V, 128), 128, 0, s>>>(lt, U, mu, col, beta, c0, c1, key, sw);
     k_sy_reunit<<<blocks(4 * lt.V, 256), 256, 0, s>>>(4 * lt.V, U);
   }
   return (int)hipGetLastError();

@@ -296,6 +296,11 @@ def test_synth_gpu_is_bitwise_cpu(S, g):
         b = S.heatbath_field_gpu(L, S.sub_seed(1040), 5.7, n).cpu().numpy()
         assert np.array_equal(a, b)
         assert np.array_equal(S.haar_gauge(L, 5, 3), S.haar_gauge_gpu(L, 5, 3).cpu().numpy())
+    # the Luscher-Weisz heatbath (eight-colour schedule)
+    for L, n in (((4, 4, 4, 4), 3), ((8, 4, 4, 4), 2)):
+        a = S.heatbath_lw_field(L, S.sub_seed(1041), 4.52, n, 0.884)
+        b = S.heatbath_lw_field_gpu(L, S.sub_seed(1041), 4.52, n, 0.884).cpu().numpy()
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec", PRECS)
