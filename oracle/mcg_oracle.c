@@ -527,6 +527,143 @@ static void subgroup_steps(ocx Y[9], ocx g[9], double omega) {
   }
 }
 
+/* ---- exact maximisation over one SU(2) subgroup (an update-rule variant) --
+ * For s = a0 + i a.sigma acting on rows (i, j) and Y_k = g M_k,
+ *   tr(s Y_k) = Y_kk' + a . b_k,  b_k = (Y_ii + Y_jj, i(Y_ji + Y_ij), Y_ji - Y_ij, i(Y_ii - Y_jj))
+ * (k' the third index), so sum_k |tr(s Y_k)|^2 = const + 2 h.a + a^T Q a with
+ * h = sum_k Re(conj(Y_k'k') b_k), Q = sum_k Re(b_k b_k^dagger).  Its maximum on
+ * the unit sphere solves (lambda - Q) a = h with lambda >= the largest
+ * eigenvalue of Q (found from the eigenvalues of Q and the secular equation
+ * sum_m (h'_m / (lambda - q_m))^2 = 1 by bisection). */
+
+/* cyclic Jacobi eigendecomposition of a real symmetric 4x4 matrix: A is
+ * overwritten by diag(q), the columns of V are the eigenvectors */
+static void sym4_eig(double A[4][4], double V[4][4]) {
+  for (int r = 0; r < 4; r++)
+    for (int c = 0; c < 4; c++) V[r][c] = r == c;
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double off = 0;
+    for (int p = 0; p < 4; p++)
+      for (int q = p + 1; q < 4; q++) off += A[p][q] * A[p][q];
+    if (off < 1e-300) break;
+    for (int p = 0; p < 4; p++)
+      for (int q = p + 1; q < 4; q++) {
+        if (A[p][q] == 0) continue;
+        double th = (A[q][q] - A[p][p]) / (2 * A[p][q]);
+        double t = (th >= 0 ? 1 : -1) / (fabs(th) + sqrt(th * th + 1));
+        double c = 1 / sqrt(t * t + 1), sn = t * c;
+        for (int k = 0; k < 4; k++) { /* A <- J^T A J */
+          double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 4; k++) {
+          double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < 4; k++) {
+          double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+/* argmax of a^T Q a + 2 h.a over |a| = 1 */
+void or_sphere_max(const double Qin[16], const double h[4], double a[4]) {
+  double A[4][4], V[4][4], q[4], hp[4];
+  for (int r = 0; r < 4; r++)
+    for (int c = 0; c < 4; c++) A[r][c] = Qin[4 * r + c];
+  sym4_eig(A, V);
+  int top = 0;
+  for (int m = 0; m < 4; m++) {
+    q[m] = A[m][m];
+    if (q[m] > q[top]) top = m;
+  }
+  double hn = 0;
+  for (int m = 0; m < 4; m++) {
+    hp[m] = 0;
+    for (int r = 0; r < 4; r++) hp[m] += V[r][m] * h[r];
+    hn += hp[m] * hp[m];
+  }
+  hn = sqrt(hn);
+  double ap[4];
+  /* phi(lambda) = sum (hp/(lambda - q))^2 falls from +inf (just above q_top)
+   * to at most 1 at lambda = q_top + |h| */
+  double lo = q[top], hi = q[top] + hn;
+  double phi_lo = 0;
+  int hard = fabs(hp[top]) <= 1e-300;
+  if (hard) { /* h has no component along the top eigenvector */
+    for (int m = 0; m < 4; m++)
+      if (m != top && q[m] < q[top]) phi_lo += (hp[m] / (q[top] - q[m])) * (hp[m] / (q[top] - q[m]));
+  }
+  if (hard && phi_lo <= 1) {
+    for (int m = 0; m < 4; m++) ap[m] = (m == top || !(q[m] < q[top])) ? 0 : hp[m] / (q[top] - q[m]);
+    ap[top] = sqrt(1 - phi_lo);
+  } else {
+    for (int it = 0; it < 200; it++) {
+      double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      double phi = 0;
+      for (int m = 0; m < 4; m++) phi += (hp[m] / (mid - q[m])) * (hp[m] / (mid - q[m]));
+      if (phi > 1) lo = mid; else hi = mid;
+    }
+    double n2 = 0;
+    for (int m = 0; m < 4; m++) {
+      ap[m] = hp[m] / (hi - q[m]);
+      n2 += ap[m] * ap[m];
+    }
+    for (int m = 0; m < 4; m++) ap[m] /= sqrt(n2);
+  }
+  for (int r = 0; r < 4; r++) {
+    a[r] = 0;
+    for (int m = 0; m < 4; m++) a[r] += V[r][m] * ap[m];
+  }
+}
+
+/* the three subgroup steps with exact maximisation, over-relaxed like the
+ * linearised ones: a = normalise((1 - omega) e0 + omega a*) */
+static void subgroup_steps_exact(const ocx M[72], ocx g[9], double omega) {
+  static const int SUB[3][2] = {{0, 1}, {1, 2}, {0, 2}};
+  for (int qq = 0; qq < 3; qq++) {
+    int i = SUB[qq][0], j = SUB[qq][1], kk = 3 - i - j;
+    double Q[16] = {0}, h[4] = {0};
+    for (int k = 0; k < 8; k++) {
+      ocx Y[9];
+      m_mul(g, M + 9 * k, Y);
+      ocx b[4] = {Y[3 * i + i] + Y[3 * j + j], I * (Y[3 * j + i] + Y[3 * i + j]), Y[3 * j + i] - Y[3 * i + j],
+                  I * (Y[3 * i + i] - Y[3 * j + j])};
+      ocx c = Y[3 * kk + kk];
+      for (int r = 0; r < 4; r++) {
+        h[r] += creal(conj(c) * b[r]);
+        for (int t = 0; t < 4; t++) Q[4 * r + t] += creal(b[r] * conj(b[t]));
+      }
+    }
+    double a[4];
+    or_sphere_max(Q, h, a);
+    a[0] = (1 - omega) + omega * a[0];
+    for (int k = 1; k < 4; k++) a[k] = omega * a[k];
+    double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+    if (na == 0) continue;
+    for (int k = 0; k < 4; k++) a[k] /= na;
+    ocx S[9];
+    m_ident(S);
+    S[3 * i + i] = a[0] + I * a[3];
+    S[3 * i + j] = a[2] + I * a[1];
+    S[3 * j + i] = -a[2] + I * a[1];
+    S[3 * j + j] = a[0] - I * a[3];
+    m_mul_left(S, g);
+  }
+}
+
+/* a site update with exact subgroup maximisation, repeated `hits` times */
+void or_site_g_exact(const ocx M[8 * 9], double omega, int hits, ocx g[9]) {
+  m_ident(g);
+  for (int h = 0; h < hits; h++) subgroup_steps_exact(M, g, omega);
+}
+
 void or_site_g(const ocx M[8 * 9], double omega, ocx g[9]) {
   ocx X[9], Y[9];
   m_zero(X);
@@ -579,13 +716,21 @@ void or_halfsweep(const int32_t L[4], ocx *W, ocx *G, int parity,
 }
 void or_halfsweep_hits(const int32_t L[4], ocx *W, ocx *G, int parity,
                        double omega, int hits) {
+  or_halfsweep_v(L, W, G, parity, omega, hits, 0);
+}
+/* exact != 0: exact per-subgroup maximisation (or_site_g_exact) */
+void or_halfsweep_v(const int32_t L[4], ocx *W, ocx *G, int parity,
+                    double omega, int hits, int exact) {
   lat_t lt = mklat(L);
 #pragma omp parallel for schedule(static)
   for (int64_t x = 0; x < lt.V; x++) {
     if (parity_of(&lt, x) != parity) continue;
     ocx M[72], g[9], gd[9];
     gather8(&lt, W, x, M);
-    or_site_g_hits(M, omega, hits, g);
+    if (exact)
+      or_site_g_exact(M, omega, hits, g);
+    else
+      or_site_g_hits(M, omega, hits, g);
     m_adj(g, gd);
     for (int mu = 0; mu < 4; mu++) {
       m_mul_left(g, link_w(W, x, mu));
@@ -632,15 +777,16 @@ int or_mcg_fix(const int32_t L[4], const ocx *U, ocx *G, double tol,
                int32_t max_sweeps, double omega, int32_t reunit_every,
                int32_t start_sweep, double *traj, or_fix_result *res) {
   return or_mcg_fix_v(L, U, G, tol, max_sweeps, omega, reunit_every,
-                      start_sweep, 1, 1, traj, res);
+                      start_sweep, 1, 1, 0, traj, res);
 }
-/* variants of the update rule: `hits` re-linearisation hits per site visit;
- * the stop test only after sweeps whose global number (start_sweep + k) is a
- * multiple of stop_every */
+/* variants of the update rule: `hits` re-linearisation hits per site visit
+ * (exact != 0: exact per-subgroup maximisation instead, repeated `hits`
+ * times); the stop test only after sweeps whose global number
+ * (start_sweep + k) is a multiple of stop_every */
 int or_mcg_fix_v(const int32_t L[4], const ocx *U, ocx *G, double tol,
                  int32_t max_sweeps, double omega, int32_t reunit_every,
                  int32_t start_sweep, int32_t hits, int32_t stop_every,
-                 double *traj, or_fix_result *res) {
+                 int32_t exact, double *traj, or_fix_result *res) {
   lat_t lt = mklat(L);
   ocx *W = malloc((size_t)lt.V * 36 * sizeof(ocx));
   or_apply_gauge(L, U, G, W);
@@ -655,8 +801,8 @@ int or_mcg_fix_v(const int32_t L[4], const ocx *U, ocx *G, double tol,
       or_apply_gauge(L, U, G, W);
       Rprev = or_functional(L, W);
     }
-    or_halfsweep_hits(L, W, G, 0, omega, hits);
-    or_halfsweep_hits(L, W, G, 1, omega, hits);
+    or_halfsweep_v(L, W, G, 0, omega, hits, exact);
+    or_halfsweep_v(L, W, G, 1, omega, hits, exact);
     double R = or_functional(L, W);
     if (traj) traj[k] = R;
     dR = R - Rprev;

@@ -86,6 +86,8 @@ void or_smear(const int32_t L[4], const ocx *U, ocx *out, double rho,
  * M[k] = W_k(x) for k < 4, M[4+mu] = W_mu(x-mu)^dagger               */
 void or_site_g(const ocx M[8 * 9], double omega, ocx g[9]);
 void or_site_g_hits(const ocx M[8 * 9], double omega, int hits, ocx g[9]);
+void or_site_g_exact(const ocx M[8 * 9], double omega, int hits, ocx g[9]);
+void or_sphere_max(const double Q[16], const double h[4], double a[4]);
 void or_site_g_at(const int32_t L[4], const ocx *W, int64_t site,
                   double omega, ocx g[9]);
 void or_halfsweep(const int32_t L[4], ocx *W, ocx *G, int parity,
@@ -96,10 +98,12 @@ int or_mcg_fix(const int32_t L[4], const ocx *U, ocx *G, double tol,
                int32_t start_sweep, double *traj, or_fix_result *res);
 void or_halfsweep_hits(const int32_t L[4], ocx *W, ocx *G, int parity,
                        double omega, int hits);
+void or_halfsweep_v(const int32_t L[4], ocx *W, ocx *G, int parity,
+                    double omega, int hits, int exact);
 int or_mcg_fix_v(const int32_t L[4], const ocx *U, ocx *G, double tol,
                  int32_t max_sweeps, double omega, int32_t reunit_every,
                  int32_t start_sweep, int32_t hits, int32_t stop_every,
-                 double *traj, or_fix_result *res);
+                 int32_t exact, double *traj, or_fix_result *res);
 
 /* ---- centre projection and P-vortices (Sec. II.A) ------------------------ */
 void or_center_project(const int32_t L[4], const ocx *U, const ocx *G,

@@ -66,7 +66,10 @@ def _declare(l):
         "or_mcg_fix": (C.c_int, [_I4, _P, _P, C.c_double, C.c_int32, C.c_double, C.c_int32,
                                  C.c_int32, _P, C.POINTER(FixResult)]),
         "or_mcg_fix_v": (C.c_int, [_I4, _P, _P, C.c_double, C.c_int32, C.c_double, C.c_int32,
-                                   C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(FixResult)]),
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, C.POINTER(FixResult)]),
+        "or_site_g_exact": (None, [_P, C.c_double, C.c_int, _P]),
+        "or_sphere_max": (None, [_P, _P, _P]),
+        "or_halfsweep_v": (None, [_I4, _P, _P, C.c_int, C.c_double, C.c_int, C.c_int]),
         "or_center_project": (None, [_I4, _P, _P, _P, _P]),
         "or_count_vortices": (None, [_I4, _P, _P, _P, _P, _P]),
         "or_vortex_field": (None, [_I4, _P, _P, _P, C.c_int, _P]),
@@ -209,6 +212,23 @@ def site_g_hits(M, omega, hits):
     return g
 
 
+def site_g_exact(M, omega, hits=1):
+    """Site update with exact maximisation over each SU(2) subgroup."""
+    M = _c128(M)
+    g = np.empty((3, 3), np.complex128)
+    lib().or_site_g_exact(_ptr(M), omega, int(hits), _ptr(g))
+    return g
+
+
+def sphere_max(Q, h):
+    """argmax over the unit sphere in R^4 of a^T Q a + 2 h.a (Q symmetric)."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    a = np.empty(4)
+    lib().or_sphere_max(_ptr(Q), _ptr(h), _ptr(a))
+    return a
+
+
 def site_g_at(W, site, omega):
     W = _c128(W)
     g = np.empty((3, 3), np.complex128)
@@ -216,13 +236,13 @@ def site_g_at(W, site, omega):
     return g
 
 
-def halfsweep(W, G, parity, omega, hits=1):
+def halfsweep(W, G, parity, omega, hits=1, exact=False):
     """In place on copies; returns (W', G')."""
     W, G = _c128(W).copy(), _c128(G).copy()
-    if hits == 1:
+    if hits == 1 and not exact:
         lib().or_halfsweep(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega)
     else:
-        lib().or_halfsweep_hits(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega, int(hits))
+        lib().or_halfsweep_v(_dims(dims_of(W)), _ptr(W), _ptr(G), int(parity), omega, int(hits), int(exact))
     return W, G
 
 
@@ -244,7 +264,7 @@ def identity_gauge(L):
 
 
 def mcg_fix(U, G0=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50,
-            start_sweep=0, want_traj=False, hits=1, stop_every=1):
+            start_sweep=0, want_traj=False, hits=1, stop_every=1, exact=False):
     """Returns (G, result dict, trajectory or None).  hits: re-linearisation
     hits per site visit; stop_every: the stop test only after sweeps whose
     global number is a multiple of it."""
@@ -253,12 +273,12 @@ def mcg_fix(U, G0=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50,
     G = identity_gauge(L) if G0 is None else _c128(G0).copy()
     traj = np.zeros(max_sweeps + 1) if want_traj else None
     res = FixResult()
-    if hits == 1 and stop_every == 1:
+    if hits == 1 and stop_every == 1 and not exact:
         lib().or_mcg_fix(_dims(L), _ptr(U), _ptr(G), tol, int(max_sweeps), omega,
                          int(reunit_every), int(start_sweep), _ptr(traj), C.byref(res))
     else:
         lib().or_mcg_fix_v(_dims(L), _ptr(U), _ptr(G), tol, int(max_sweeps), omega, int(reunit_every),
-                           int(start_sweep), int(hits), int(stop_every), _ptr(traj), C.byref(res))
+                           int(start_sweep), int(hits), int(stop_every), int(exact), _ptr(traj), C.byref(res))
     info = dict(R=res.R, dR=res.dR, theta=res.theta, sweeps=res.sweeps, status=res.status)
     if traj is not None:
         traj = traj[: res.sweeps + 1].copy()
