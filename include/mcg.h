@@ -246,6 +246,15 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * (start_sweep + k) is a multiple of this, e.g. 50 for whole blocks. */
 #define MCG_OPT_HITS 3
 #define MCG_OPT_STOP_EVERY 4
+/* MCG_OPT_EXACT (0/1, default 0): each subgroup step maximises
+ * sum_k |tr(s g M_k)|^2 over its SU(2) subgroup exactly instead of the
+ * linearised functional (then over-relaxes the same way; with omega > 1
+ * monotonicity is no longer guaranteed).  The subgroup functional is
+ * const + 2 h.a + a^T Q a on the unit 3-sphere; its maximiser comes from the
+ * eigendecomposition of the 4x4 Q and a secular equation, in FP64.  Combined
+ * with MCG_OPT_HITS, the three exact steps repeat `hits` times.  Runs with
+ * 256-thread blocks. */
+#define MCG_OPT_EXACT 7
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,
  * vortex_field, wilson_loops, smear_mcg_backward) first checks them and

@@ -599,7 +599,9 @@ void or_sphere_max(const double Qin[16], const double h[4], double a[4]) {
     for (int m = 0; m < 4; m++)
       if (m != top && q[m] < q[top]) phi_lo += (hp[m] / (q[top] - q[m])) * (hp[m] / (q[top] - q[m]));
   }
-  if (hard && phi_lo <= 1) {
+  if (!(hi > lo)) { /* |h| negligible against q_top: the top eigenvector */
+    for (int m = 0; m < 4; m++) ap[m] = m == top;
+  } else if (hard && phi_lo <= 1) {
     for (int m = 0; m < 4; m++) ap[m] = (m == top || !(q[m] < q[top])) ? 0 : hp[m] / (q[top] - q[m]);
     ap[top] = sqrt(1 - phi_lo);
   } else {

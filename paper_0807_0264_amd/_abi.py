@@ -18,6 +18,7 @@ MCG_OPT_HITS = 3
 MCG_OPT_STOP_EVERY = 4
 MCG_OPT_CHECK = 5
 MCG_OPT_SCRATCH_LIMIT_MIB = 6
+MCG_OPT_EXACT = 7
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 

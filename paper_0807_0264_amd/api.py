@@ -428,21 +428,25 @@ def set_scratch_limit_mib(mib, device=None):
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SCRATCH_LIMIT_MIB, int(mib)), ctx)
 
 
-def set_update_variant(hits=1, stop_every=1, device=None):
+def set_update_variant(hits=1, stop_every=1, exact=False, device=None):
     """Update-rule variants of the fixing loop: `hits` re-linearisation hits
-    per site visit, and the stop test only after sweeps numbered by multiples
-    of `stop_every` (1, 1: the plain method)."""
+    per site visit, the stop test only after sweeps numbered by multiples of
+    `stop_every`, and exact maximisation over each SU(2) subgroup (1, 1,
+    False: the plain method)."""
     ctx = context(device)
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_HITS, int(hits)), ctx)
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_STOP_EVERY, int(stop_every)), ctx)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_EXACT, 1 if exact else 0), ctx)
 
 
 def get_update_variant(device=None):
+    """(hits, stop_every, exact) as set by set_update_variant."""
     ctx = context(device)
-    h, s = C.c_int32(), C.c_int32()
+    h, s, e = C.c_int32(), C.c_int32(), C.c_int32()
     _check(A.load().mcg_get_option(ctx, A.MCG_OPT_HITS, C.byref(h)), ctx)
     _check(A.load().mcg_get_option(ctx, A.MCG_OPT_STOP_EVERY, C.byref(s)), ctx)
-    return h.value, s.value
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_EXACT, C.byref(e)), ctx)
+    return h.value, s.value, bool(e.value)
 
 
 def get_slabs(device=None):

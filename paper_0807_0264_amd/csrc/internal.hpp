@@ -16,9 +16,10 @@ constexpr int NUM_VARIANTS = 6;
 inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 256); }
 template <typename T>
 // slab < 0: the whole of every field (blocks = total); slab >= 0: that slab's chunks (blocks = their total)
-// hits > 1 (re-linearisation hits) requires variant 2 (256-thread blocks)
+// hits > 1 (re-linearisation hits) or exact (exact subgroup maximisation) requires variant 2
+// (256-thread blocks)
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1);
+                            bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0);
 template <typename T>
 hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s);
 template <typename T>

@@ -26,16 +26,25 @@ namespace mcg {
 // c12: working field and transform stored as two rows
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab, int hits) {
+                            bool withR, bool gated, hipStream_t s, int slab, int hits, int exact) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
-  if (hits > 1) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
+  if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
-#define MCG_HM(WR, C) k_halfsweep<T, 256, WR, 1, C, true><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, hits)
-    if (c12) {
-      if (withR) MCG_HM(true, true); else MCG_HM(false, true);
+#define MCG_HM(WR, C, E) \
+  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, hits)
+    if (exact) {
+      if (c12) {
+        if (withR) MCG_HM(true, true, true); else MCG_HM(false, true, true);
+      } else {
+        if (withR) MCG_HM(true, false, true); else MCG_HM(false, false, true);
+      }
     } else {
-      if (withR) MCG_HM(true, false); else MCG_HM(false, false);
+      if (c12) {
+        if (withR) MCG_HM(true, true, false); else MCG_HM(false, true, false);
+      } else {
+        if (withR) MCG_HM(true, false, false); else MCG_HM(false, false, false);
+      }
     }
 #undef MCG_HM
     return hipGetLastError();
@@ -112,7 +121,7 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t, int, int);                                    \
+                                          hipStream_t, int, int, int);                               \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
   template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \

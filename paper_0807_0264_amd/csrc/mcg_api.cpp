@@ -40,6 +40,7 @@ struct mcg_ctx {
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
+  bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
   size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
   size_t scratch_used = 0;
@@ -242,11 +243,12 @@ template <typename T> struct FixRun {
   int grid[MAX_SLABS] = {};
   bool gated = true;
   int hits = 1;
+  int exact = 0;
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
     if (blocks > 0)
-      HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits));
+      HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact));
     return MCG_OK;
   }
   // Even then odd half-sweep.  Slab by slab (n > 1), in the order E0 E1 [E(k) O(k-1)] for
@@ -308,7 +310,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   }
   const bool c12 = ctx->c12;
   // re-linearisation hits run in one instantiation with 256-thread blocks (variant 2)
-  const int variant = ctx->hits > 1 ? 2 : ctx->variant[prec][c12], bs = variant_block(variant);
+  const int variant = (ctx->hits > 1 || ctx->exact) ? 2 : ctx->variant[prec][c12], bs = variant_block(variant);
   if ((int)ctx->W.size() < B) {
     ctx->W.resize(B);
     ctx->G12.resize(B);
@@ -354,6 +356,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
   run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
   run.hits = ctx->hits;
+  run.exact = ctx->exact ? 1 : 0;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -807,7 +810,8 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
                                  hipStream_t s, int n = 1) {
   const Geom g = geom_of(W->d);
   const bool c12 = parity < 0 && ctx->c12;
-  const int variant = ctx->hits > 1 ? 2 : ctx->variant[W->prec][c12], nb = nblocks(g, variant_block(variant));
+  const int variant = (ctx->hits > 1 || ctx->exact) ? 2 : ctx->variant[W->prec][c12],
+            nb = nblocks(g, variant_block(variant));
   mcg_status st;
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>))) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>))))
     return st;
@@ -826,10 +830,12 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   FixRun<T> run{ctx, s, 1, variant, variant_block(variant), nb, c12, ctx->desc.p, omega};
   run.gated = false;
   run.hits = ctx->hits;
+  run.exact = ctx->exact ? 1 : 0;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
-    HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s, -1, ctx->hits));
+    HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s, -1, ctx->hits,
+                               ctx->exact ? 1 : 0));
     return MCG_OK;
   }
   if (c12) {
@@ -963,6 +969,11 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->nslab = value;
     return MCG_OK;
   }
+  if (option == MCG_OPT_EXACT) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_EXACT takes 0 or 1");
+    ctx->exact = value != 0;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_CHECK) {
     if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_CHECK takes 0 or 1");
     ctx->check = value != 0;
@@ -1003,6 +1014,10 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   }
   if (option == MCG_OPT_CHECK) {
     *value = ctx->check ? 1 : 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_EXACT) {
+    *value = ctx->exact ? 1 : 0;
     return MCG_OK;
   }
   if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {

@@ -83,6 +83,171 @@ template <typename T> __device__ __forceinline__ M3<T> local_update(M3<T> Y, T o
   return g;
 }
 
+// ------------------------------------------- exact subgroup maximisation
+// argmax over the unit sphere of R^4 of a^T Q a + 2 h.a (Q symmetric, destroyed): cyclic Jacobi
+// eigendecomposition Q = V diag(q) V^T, then the secular equation sum_m (h'_m / (lam - q_m))^2 = 1,
+// h' = V^T h, for lam in [q_top, q_top + |h|] by bisection; a = V h' / (lam - q), normalised.  When h
+// has no component along the top eigenvector and the rest of a is shorter than 1, lam = q_top.
+__device__ __forceinline__ void sphere_max(double Q[4][4], const double h[4], double a[4]) {
+  double V[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; r++)
+#pragma unroll
+    for (int c = 0; c < 4; c++) V[r][c] = r == c ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 10; sweep++) {
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+      for (int q = p + 1; q < 4; q++) {
+        const double apq = Q[p][q];
+        if (fabs(apq) > 1e-300) {
+          const double th = (Q[q][q] - Q[p][p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const double akp = Q[k][p], akq = Q[k][q];
+            Q[k][p] = c * akp - sn * akq;
+            Q[k][q] = sn * akp + c * akq;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const double apk = Q[p][k], aqk = Q[q][k];
+            Q[p][k] = c * apk - sn * aqk;
+            Q[q][k] = sn * apk + c * aqk;
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const double vkp = V[k][p], vkq = V[k][q];
+            V[k][p] = c * vkp - sn * vkq;
+            V[k][q] = sn * vkp + c * vkq;
+          }
+        }
+      }
+  }
+  double q[4], hp[4], hn = 0.0, qtop = Q[0][0];
+  int top = 0;
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    q[m] = Q[m][m];
+    if (q[m] > qtop) {
+      qtop = q[m];
+      top = m;
+    }
+    hp[m] = V[0][m] * h[0] + V[1][m] * h[1] + V[2][m] * h[2] + V[3][m] * h[3];
+    hn += hp[m] * hp[m];
+  }
+  double htop = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; m++)
+    if (m == top) htop = hp[m];
+  double ap[4];
+  double rest = 0.0;
+  if (fabs(htop) <= 1e-300) {
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+      if (m != top && q[m] < qtop) rest += (hp[m] / (qtop - q[m])) * (hp[m] / (qtop - q[m]));
+  }
+  if (!(qtop + sqrt(hn) > qtop)) {  // |h| negligible against q_top: the top eigenvector
+#pragma unroll
+    for (int m = 0; m < 4; m++) ap[m] = m == top ? 1.0 : 0.0;
+  } else if (fabs(htop) <= 1e-300 && rest <= 1.0) {
+#pragma unroll
+    for (int m = 0; m < 4; m++) ap[m] = (m == top || !(q[m] < qtop)) ? 0.0 : hp[m] / (qtop - q[m]);
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+      if (m == top) ap[m] = sqrt(1.0 - rest);
+  } else {
+    double lo = qtop, hi = qtop + sqrt(hn);
+    for (int it = 0; it < 80; it++) {
+      const double mid = 0.5 * (lo + hi);
+      double phi = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; m++) phi += (hp[m] / (mid - q[m])) * (hp[m] / (mid - q[m]));
+      if (phi > 1.0) lo = mid; else hi = mid;
+    }
+    double n2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+      ap[m] = hp[m] / (hi - q[m]);
+      n2 += ap[m] * ap[m];
+    }
+    const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int m = 0; m < 4; m++) ap[m] *= inv;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; r++) a[r] = V[r][0] * ap[0] + V[r][1] * ap[1] + V[r][2] * ap[2] + V[r][3] * ap[3];
+}
+
+// Y = g M restricted to what tr(s Y) needs for subgroup (I, J): with K the third index,
+// tr(s Y) = Y_KK + a.b, b = (Y_II + Y_JJ, i(Y_JI + Y_IJ), Y_JI - Y_IJ, i(Y_II - Y_JJ)); adds
+// Re(conj(Y_KK) b) to h and Re(b b^dagger) to Q.  ND: M = m^dagger.
+template <typename T, int I, int J, bool ND>
+__device__ __forceinline__ void subgroup_form(const M3<T> &g, const M3<T> &m, double Q[4][4], double h[4]) {
+  constexpr int K = 3 - I - J;
+  auto Mel = [&](int r, int c) -> cx<double> {
+    const cx<T> v = ND ? conj(m.e[3 * c + r]) : m.e[3 * r + c];
+    return cx<double>{(double)v.re, (double)v.im};
+  };
+  auto Yel = [&](int r, int c) -> cx<double> {
+    cx<double> s{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      const cx<T> gv = g.e[3 * r + k];
+      s = s + cx<double>{(double)gv.re, (double)gv.im} * Mel(k, c);
+    }
+    return s;
+  };
+  const cx<double> yii = Yel(I, I), yjj = Yel(J, J), yij = Yel(I, J), yji = Yel(J, I), ykk = Yel(K, K);
+  const cx<double> s1 = yji + yij, s3 = yii - yjj;
+  const cx<double> b[4] = {yii + yjj, cx<double>{-s1.im, s1.re}, yji - yij, cx<double>{-s3.im, s3.re}};
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    h[r] += ykk.re * b[r].re + ykk.im * b[r].im;
+#pragma unroll
+    for (int c = 0; c < 4; c++) Q[r][c] += b[r].re * b[c].re + b[r].im * b[c].im;
+  }
+}
+
+// One exact subgroup step on (I, J), over-relaxed: g <- s g.
+template <typename T, int I, int J, bool C12>
+__device__ __forceinline__ void exact_step(const M3<T> F[4], const M3<T> Bk[4], M3<T> &g, T omega) {
+  double Q[4][4], h[4];
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    h[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) Q[r][c] = 0.0;
+  }
+#pragma unroll
+  for (int mu = 0; mu < 4; mu++) {
+    M3<T> f = F[mu];
+    if constexpr (C12) third_row(f);
+    subgroup_form<T, I, J, false>(g, f, Q, h);
+    M3<T> bk = Bk[mu];
+    if constexpr (C12) third_row(bk);
+    subgroup_form<T, I, J, true>(g, bk, Q, h);
+  }
+  double a[4];
+  sphere_max(Q, h, a);
+  const double w = (double)omega;
+  a[0] = (1.0 - w) + w * a[0];
+  a[1] *= w;
+  a[2] *= w;
+  a[3] *= w;
+  const double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+  if (!(na > 0.0)) return;
+  const T a0 = (T)(a[0] / na), a1 = (T)(a[1] / na), a2 = (T)(a[2] / na), a3 = (T)(a[3] / na);
+  const cx<T> s00{a0, a3}, s01{a2, a1}, s10{-a2, a1}, s11{a0, -a3};
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const cx<T> gi = g.e[3 * I + c], gj = g.e[3 * J + c];
+    g.e[3 * I + c] = s00 * gi + s01 * gj;
+    g.e[3 * J + c] = s10 * gi + s11 * gj;
+  }
+}
+
 // X += t * B^dagger
 template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3<T> &b, M3<T> &X) {
 #pragma unroll
@@ -103,8 +268,9 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // slab >= 0: this launch covers only that slab's chunk of every field (see LatDesc).
 // MULTI: `hits` re-linearisation hits per site: after the first update each further hit
 // linearises sum_k |tr(g M_k)|^2 at the current g, X_g = sum_k conj(tr(g M_k)) M_k, and runs
-// the subgroup steps on g X_g, continuing g.
-template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false>
+// the subgroup steps on g X_g, continuing g.  EXACT: each subgroup step instead maximises
+// sum_k |tr(s g M_k)|^2 over its subgroup exactly (then over-relaxes), `hits` rounds of three.
+template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
                                                        T omega, int gated, int slab, int hits = 1) {
   using WS = typename FixStore<T, C12>::W;
@@ -153,8 +319,18 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       if constexpr (C12) third_row(bk);
       axpy_dag(trace(bk), bk, X);
     }
-    M3<T> g = local_update<T>(X, omega);
-    if constexpr (MULTI) {
+    M3<T> g;
+    if constexpr (EXACT) {
+      g = m_ident<T>();
+      for (int it = 0; it < hits; it++) {
+        exact_step<T, 0, 1, C12>(F, Bk, g, omega);
+        exact_step<T, 1, 2, C12>(F, Bk, g, omega);
+        exact_step<T, 0, 2, C12>(F, Bk, g, omega);
+      }
+    } else {
+      g = local_update<T>(X, omega);
+    }
+    if constexpr (MULTI && !EXACT) {
       for (int it = 1; it < hits; it++) {
         M3<T> Xh = m_zero<T>();
 #pragma unroll

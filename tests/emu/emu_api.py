@@ -262,9 +262,10 @@ def set_variant(prec, v):
     check(lib().mcg_set_variant(ctx(), prec, v))
 
 
-def set_update_variant(hits, stop_every):
+def set_update_variant(hits, stop_every, exact=False):
     check(lib().mcg_set_option(ctx(), 3, hits))
     check(lib().mcg_set_option(ctx(), 4, stop_every))
+    check(lib().mcg_set_option(ctx(), 7, 1 if exact else 0))
 
 
 def set_check(on):

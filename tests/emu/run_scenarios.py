@@ -200,25 +200,29 @@ def scenario_slabs(prec):
 
 
 def scenario_variants(prec):
-    """Re-linearisation hits and the block-wise stop test against the oracle."""
+    """Re-linearisation hits, exact subgroup maximisation and the block-wise
+    stop test against the oracle."""
     L = (4, 4, 4, 4)
     U = rounded(field(L, 2070), prec)
-    for hits, stop_every in ((2, 1), (3, 4)):
-        E.set_update_variant(hits, stop_every)
+    for hits, stop_every, exact, omega in ((2, 1, False, 1.7), (3, 4, False, 1.7), (1, 1, True, 1.0),
+                                           (2, 3, True, 1.7)):
+        E.set_update_variant(hits, stop_every, exact)
+        what = f"hits={hits} exact={exact}"
         for two_row in (True, False):
             E.set_two_row(two_row)
-            G, info = E.fix(E.links(U, prec), None, tol=1e-4, max_sweeps=9, reunit_every=4, check_every=3)
-            Go, io, to = O.mcg_fix(U, tol=1e-4, max_sweeps=9, reunit_every=4, want_traj=True, hits=hits,
-                                   stop_every=stop_every)
-            check(info["sweeps"] == io["sweeps"], f"sweeps {info['sweeps']} {io['sweeps']} hits={hits}")
-            check((np.abs(info["traj"] - to) / to).max() < TOL[prec], f"trajectory hits={hits}")
+            G, info = E.fix(E.links(U, prec), None, tol=1e-4, max_sweeps=9, omega=omega, reunit_every=4,
+                            check_every=3)
+            Go, io, to = O.mcg_fix(U, tol=1e-4, max_sweeps=9, omega=omega, reunit_every=4, want_traj=True,
+                                   hits=hits, stop_every=stop_every, exact=exact)
+            check(info["sweeps"] == io["sweeps"], f"sweeps {info['sweeps']} {io['sweeps']} {what}")
+            check((np.abs(info["traj"] - to) / to).max() < TOL[prec], f"trajectory {what}")
             if prec == 0:
-                check(np.abs(E.host_gauge(G) - Go).max() < 1e-11, "final G")
+                check(np.abs(E.host_gauge(G) - Go).max() < 1e-11, f"final G {what}")
         W, Gd = E.links(U, prec), E.gauge_identity(L)
-        E.halfsweep(W, Gd, 1)
+        E.halfsweep(W, Gd, 1, omega)
         Wo, Ho = O.halfsweep(U, np.broadcast_to(np.eye(3), (L[3], L[2], L[1], L[0], 3, 3)).copy(),
-                             1, 1.7, hits=hits)
-        check(np.abs(E.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 2e-5), f"halfsweep hits={hits}")
+                             1, omega, hits=hits, exact=exact)
+        check(np.abs(E.host_links(W) - Wo).max() < (1e-13 if prec == 0 else 2e-5), f"halfsweep {what}")
     E.set_update_variant(1, 1)
     E.set_two_row(True)
 

@@ -371,6 +371,59 @@ def test_update_variants(S, O, g, api, L, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 6, 6, 10)])
+def test_exact_update(S, O, g, api, L, prec):
+    """Exact maximisation over each SU(2) subgroup (omega = 1 and over-relaxed,
+    one and two rounds of the three subgroups, with a block-wise stop) against
+    the oracle: trajectory, stop sweep and transform, and two sweeps of W.
+
+    The exact step is worse conditioned than the linearised one: where the
+    root of the secular equation lies close to the second eigenvalue of the
+    4x4 form, rounding of the form rotates the maximiser.  Measured on the
+    oracle itself (FP64) on these inputs: relative noise of 1e-15 on U moves
+    W by up to 7e-12 after two sweeps (linearised update: 2e-13), hence the
+    FP64 bound 2e-11 on W, and noise of 6e-8 by up to 3e-5 (linearised:
+    1.5e-6), hence the FP32 bound 1e-4; with omega = 1.7 a relative 1e-7
+    grows to 2e-6 of R by sweep 20 and 2e-4 by sweep 60 (linearised: 6e-7),
+    so over-relaxed FP32 trajectories are compared element-wise over the
+    first 20 sweeps and at the end within 1e-3.  Over a 60-sweep fix, noise
+    of 1e-15 moves the oracle's transform by up to 2.6e-9 and its relative
+    trajectory by 8e-13 (omega = 1.7 on 6x6x6x10), hence the FP64 bounds
+    2e-8 on G and 1e-11 on R."""
+    U = g.rounded(field(S, L, 1065), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1066))
+    try:
+        for hits, stop_every, omega in ((1, 1, 1.0), (1, 1, 1.7), (2, 10, 1.0)):
+            api.set_update_variant(hits, stop_every, exact=True)
+            assert api.get_update_variant() == (hits, stop_every, True)
+            Go, io, to = O.mcg_fix(U, G0, tol=1e-6, max_sweeps=60, omega=omega, reunit_every=20,
+                                   want_traj=True, hits=hits, stop_every=stop_every, exact=True)
+            for two_row in (True, False):
+                api.set_two_row(two_row)
+                G, info = api.fix(g.links(U, prec), g.gauge(G0), tol=1e-6, max_sweeps=60, omega=omega,
+                                  reunit_every=20, check_every=7, want_traj=True)
+                n = min(info["sweeps"], io["sweeps"]) + 1
+                tol = 1e-11 if prec == 0 else 3e-5
+                m = n if prec == 0 or omega == 1.0 else min(n, 21)
+                assert (np.abs(info["traj"][:m] - to[:m]) / to[:m]).max() < tol, (hits, omega)
+                assert abs(info["traj"][n - 1] - to[n - 1]) / to[n - 1] < (tol if prec == 0 else 1e-3)
+                if prec == 0:
+                    assert info["status"] == io["status"] and info["sweeps"] == io["sweeps"]
+                    assert np.abs(g.host_gauge(G) - Go).max() < 2e-8
+                if info["status"] == 0:
+                    assert info["sweeps"] % stop_every == 0
+            W, Gd = g.links(U, prec), g.gauge(G0)
+            api.sweeps(W, Gd, 2, omega)
+            Wo, Ho = U.copy(), G0.copy()
+            for par in (0, 1, 0, 1):
+                Wo, Ho = O.halfsweep(Wo, Ho, par, omega, hits=hits, exact=True)
+            assert np.abs(g.host_links(W) - Wo).max() < (2e-11 if prec == 0 else 1e-4)
+    finally:
+        api.set_update_variant(1, 1)
+        api.set_two_row(True)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_fix_is_bitwise_across_launch_variants(S, g, api, prec):
     """The FP64 partial sums of R are per 64-site wavefront in index order, so
     the block size and occupancy of the launch do not change any bit of the
