@@ -314,7 +314,9 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
             traffic = pmc.get("hbm_bytes_per_launch")
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_halfsweep<float,%s> (one parity of 32^3x64)" % ("two-row" if two_row else "full"),
+                kernel="k_halfsweep<float,%s> (one parity of 32^3x64, %s)" % (
+                    "two-row" if two_row else "full",
+                    "alternating tile order" if api.get_sweep_order() else "forward tile order"),
                 ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps)
 
 
@@ -464,6 +466,8 @@ def main():
                                      "batched MCG fix to dR<1e-7 (omega=1.7), carried-back batched "
                                      "re-fix, centre projection, vortex count",
                             links="fp32", gauge="fp64", reductions="fp64", half_sweep_variant=best,
+                            sweep_order="odd half-sweeps in reverse tile order" if api.get_sweep_order()
+                            else "forward",
                             per_field=[dict(L=x["L"], sweeps_smeared=x["sweeps_smeared"], sweeps=x["sweeps"],
                                             R_smeared=round(x["R_smeared"], 7), R=round(x["R"], 7),
                                             vortex_fraction=round(x["vortex_fraction"], 5))

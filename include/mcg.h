@@ -255,6 +255,15 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * with MCG_OPT_HITS, the three exact steps repeat `hits` times.  Runs with
  * 256-thread blocks. */
 #define MCG_OPT_EXACT 7
+/* MCG_OPT_ORDER (0/1, default 1): 1 makes every odd half-sweep visit the
+ * lattice tiles in reverse order, so it starts on the links the even
+ * half-sweep wrote last (and the next even half-sweep on those the odd one
+ * wrote last), which the last-level cache may still hold; the reversal keeps
+ * each tile on the XCD that handles it in the forward order.  0: every
+ * half-sweep in forward order.  Results are bit-identical for both: the sites
+ * of one parity are independent and the reduction partials belong to tiles,
+ * not to the launch order. */
+#define MCG_OPT_ORDER 8
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,
  * vortex_field, wilson_loops, smear_mcg_backward) first checks them and

@@ -19,6 +19,7 @@ MCG_OPT_STOP_EVERY = 4
 MCG_OPT_CHECK = 5
 MCG_OPT_SCRATCH_LIMIT_MIB = 6
 MCG_OPT_EXACT = 7
+MCG_OPT_ORDER = 8
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 

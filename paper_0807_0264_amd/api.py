@@ -402,6 +402,20 @@ def set_slabs(n, device=None):
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_SLABS, int(n)), ctx)
 
 
+def set_sweep_order(alternate, device=None):
+    """alternate=True: odd half-sweeps visit the lattice tiles in reverse
+    order, starting where the even half-sweep ended (bit-identical results)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_ORDER, 1 if alternate else 0), ctx)
+
+
+def get_sweep_order(device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_ORDER, C.byref(v)), ctx)
+    return bool(v.value)
+
+
 def unitarity(U=None, G=None):
     """(max |U U^dag - 1|, max |G G^dag - 1|) over all links / matrices (inf for NaN)."""
     if U is None and G is None:

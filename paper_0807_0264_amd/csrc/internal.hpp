@@ -17,9 +17,10 @@ inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 2
 template <typename T>
 // slab < 0: the whole of every field (blocks = total); slab >= 0: that slab's chunks (blocks = their total)
 // hits > 1 (re-linearisation hits) or exact (exact subgroup maximisation) requires variant 2
-// (256-thread blocks)
+// (256-thread blocks); rev: tiles in reverse grid order (same results, other visiting order)
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0);
+                            bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0,
+                            int rev = 0);
 template <typename T>
 hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s);
 template <typename T>

@@ -26,13 +26,13 @@ namespace mcg {
 // c12: working field and transform stored as two rows
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab, int hits, int exact) {
+                            bool withR, bool gated, hipStream_t s, int slab, int hits, int exact, int rev) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
   if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
 #define MCG_HM(WR, C, E) \
-  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, hits)
+  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, hits)
     if (exact) {
       if (c12) {
         if (withR) MCG_HM(true, true, true); else MCG_HM(false, true, true);
@@ -50,7 +50,7 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
     return hipGetLastError();
   }
 #define MCG_HS(WR, OCC, C)                                                                         \
-  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab)))
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev)))
   if (c12) {
     if (variant / 3 == 0) {
       if (withR) { MCG_HS(true, 1, true); } else { MCG_HS(false, 1, true); }
@@ -121,7 +121,7 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t, int, int, int);                               \
+                                          hipStream_t, int, int, int, int);                          \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
   template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \

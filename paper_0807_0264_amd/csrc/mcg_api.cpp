@@ -41,6 +41,7 @@ struct mcg_ctx {
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
+  int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order (MCG_OPT_ORDER)
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
   size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
   size_t scratch_used = 0;
@@ -244,11 +245,13 @@ template <typename T> struct FixRun {
   bool gated = true;
   int hits = 1;
   int exact = 0;
+  int order = 0;
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
     if (blocks > 0)
-      HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact));
+      HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact,
+                                 order && par == 1));
     return MCG_OK;
   }
   // Even then odd half-sweep.  Slab by slab (n > 1), in the order E0 E1 [E(k) O(k-1)] for
@@ -357,6 +360,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
+  run.order = ctx->order;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -831,11 +835,12 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   run.gated = false;
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
+  run.order = ctx->order;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
     HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s, -1, ctx->hits,
-                               ctx->exact ? 1 : 0));
+                               ctx->exact ? 1 : 0, ctx->order && parity == 1));
     return MCG_OK;
   }
   if (c12) {
@@ -903,11 +908,13 @@ static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best,
     hipError_t e = hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int k = 0; k < 4 && e == hipSuccess; k++)
-      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s, -1, 1, 0,
+                              ctx->order && (k & 1));
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     const int reps = 8;
     for (int k = 0; k < reps && e == hipSuccess; k++)
-      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s);
+      e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s, -1, 1, 0,
+                              ctx->order && (k & 1));
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
@@ -974,6 +981,11 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->exact = value != 0;
     return MCG_OK;
   }
+  if (option == MCG_OPT_ORDER) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_ORDER takes 0 or 1");
+    ctx->order = value;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_CHECK) {
     if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_CHECK takes 0 or 1");
     ctx->check = value != 0;
@@ -1018,6 +1030,10 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   }
   if (option == MCG_OPT_EXACT) {
     *value = ctx->exact ? 1 : 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_ORDER) {
+    *value = ctx->order;
     return MCG_OK;
   }
   if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {

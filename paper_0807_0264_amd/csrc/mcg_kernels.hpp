@@ -17,18 +17,36 @@ __device__ __forceinline__ int find_field(const LatDesc<T> *__restrict__ D, int 
 // The field of this grid block and the block's index within the field: the
 // whole-field mapping for slab < 0, else the chunk of slab `slab`.  A field
 // whose chunk is empty has the same start as the next one and is skipped.
+// rev: the tiles in reverse dispatch order, so a launch that follows one in
+// the forward order starts on the tiles its predecessor touched last (which
+// the last-level cache may still hold).  Workgroups are dealt to the eight
+// XCDs in turn (block i to XCD i mod 8), so the reversal runs within each
+// residue class mod 8: grid block x + 8j takes tile x + 8(c_x - 1 - j), c_x
+// the number of blocks of residue x; every tile stays on the XCD (and its
+// L2) that handles it in the forward order.
+__device__ __forceinline__ int tile_of_block(int rev) {
+  const int b = (int)blockIdx.x;
+  if (!rev) return b;
+  const int n = (int)gridDim.x, x = b & 7;
+  const int cx = (n >> 3) + (x < (n & 7) ? 1 : 0);
+  return x + 8 * (cx - 1 - (b >> 3));
+}
+
 template <typename T>
-__device__ __forceinline__ int block_of(const LatDesc<T> *__restrict__ D, int B, int slab, int &local) {
+__device__ __forceinline__ int block_of(const LatDesc<T> *__restrict__ D, int B, int slab, int rev, int &local) {
+  const int vb = tile_of_block(rev);
   if (slab < 0) {
-    const int b = find_field(D, B);
-    local = (int)blockIdx.x - D[b].blk0;
+    int b = 0;
+    for (int i = 1; i < B; i++)
+      if (vb >= D[i].blk0) b = i;
+    local = vb - D[b].blk0;
     return b;
   }
   int b = 0;
   for (int i = 1; i < B; i++)
-    if ((int)blockIdx.x >= D[i].sblk0[slab]) b = i;
+    if (vb >= D[i].sblk0[slab]) b = i;
   const int lo = D[b].nslab > 1 ? (slab * D[b].nblk) / D[b].nslab : 0;
-  local = lo + (int)blockIdx.x - D[b].sblk0[slab];
+  local = lo + vb - D[b].sblk0[slab];
   return b;
 }
 
@@ -272,11 +290,11 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // sum_k |tr(s g M_k)|^2 over its subgroup exactly (then over-relaxes), `hits` rounds of three.
 template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
-                                                       T omega, int gated, int slab, int hits = 1) {
+                                                       T omega, int gated, int slab, int rev, int hits = 1) {
   using WS = typename FixStore<T, C12>::W;
   using GS = typename FixStore<T, C12>::G;
   int lb;
-  const int b = block_of(D, B, slab, lb);
+  const int b = block_of(D, B, slab, rev, lb);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
   const int h = lb * BS + (int)threadIdx.x;

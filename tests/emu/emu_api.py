@@ -268,6 +268,10 @@ def set_update_variant(hits, stop_every, exact=False):
     check(lib().mcg_set_option(ctx(), 7, 1 if exact else 0))
 
 
+def set_sweep_order(alternate):
+    check(lib().mcg_set_option(ctx(), 8, 1 if alternate else 0))
+
+
 def set_check(on):
     check(lib().mcg_set_option(ctx(), 5, 1 if on else 0))
 

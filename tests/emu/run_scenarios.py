@@ -176,14 +176,16 @@ def scenario_loops(L, prec):
 
 
 def scenario_slabs(prec):
-    """Slab-pipelined half-sweeps give the bits of whole half-sweeps."""
+    """Slab-pipelined half-sweeps, and odd half-sweeps in reverse tile order,
+    give the bits of whole forward half-sweeps."""
     L1, L2 = (4, 4, 4, 16), (2, 2, 2, 2)
     U1, U2 = rounded(field(L1, 2060), prec), rounded(field(L2, 2061), prec)
     G1 = S.haar_gauge(L1, S.sub_seed(2062))
     E.set_variant(prec, 0)  # 64-thread blocks: 8 blocks per half-sweep of L1, split into 2 or 3 slabs
     ref = None
-    for n in (1, 2, 3):
+    for n, order in ((1, 0), (2, 0), (3, 0), (1, 1), (3, 1)):
         E.set_slabs(n)
+        E.set_sweep_order(order)
         G, info = E.fix(E.links(U1, prec), E.gauge(G1), tol=-1.0, max_sweeps=5, reunit_every=2, check_every=2)
         infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], [E.gauge_identity(L2), E.gauge(G1)],
                             [-1.0, -1.0], [4, 5], reunit_every=2, check_every=2)
@@ -194,8 +196,19 @@ def scenario_slabs(prec):
             ref = got
             check(np.array_equal(got[1], got[3]), "batch equals single")
         else:
-            check(all(np.array_equal(a, b) for a, b in zip(got, ref)), f"slabs {n} differ from whole half-sweeps")
+            check(all(np.array_equal(a, b) for a, b in zip(got, ref)),
+                  f"slabs {n} order {order} differ from whole forward half-sweeps")
     E.set_slabs(1)
+    # 20 blocks of 64 sites per half-sweep: residue classes mod 8 of three and two blocks
+    L3 = (4, 4, 4, 40)
+    U3 = rounded(field(L3, 2063), prec)
+    got = []
+    for order in (0, 1):
+        E.set_sweep_order(order)
+        G, info = E.fix(E.links(U3, prec), None, tol=-1.0, max_sweeps=4, reunit_every=2, check_every=2)
+        got.append((E.host_gauge(G), info["traj"]))
+    check(all(np.array_equal(a, b) for a, b in zip(*got)), "reverse tile order differs on 20 blocks")
+    E.set_sweep_order(0)
     E.set_variant(prec, 2)
 
 

@@ -306,15 +306,18 @@ def test_synth_gpu_is_bitwise_cpu(S, g):
 @pytest.mark.parametrize("prec", PRECS)
 def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
     """Half-sweeps run slab by slab (several slab counts, a batch mixing a
-    split and an unsplit field) give the bits of whole half-sweeps."""
+    split and an unsplit field), and odd half-sweeps in reverse tile order,
+    give the bits of whole forward half-sweeps."""
     L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
     U1 = g.rounded(field(S, L1, 1050), prec)
     U2 = g.rounded(field(S, L2, 1051), prec)
     G1 = S.haar_gauge(L1, S.sub_seed(1052))
     ref = None
     try:
-        for n in (1, 2, 5, 8):
+        for n, order in ((1, False), (2, False), (5, False), (8, False), (1, True), (5, True)):
             api.set_slabs(n)
+            api.set_sweep_order(order)
+            assert api.get_sweep_order() == order
             G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=60, reunit_every=25,
                               check_every=20, want_traj=True)
             Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)], [api.gauge_identity(L2), g.gauge(G1)],
@@ -329,9 +332,10 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
                 assert np.array_equal(got[1], got[3]) and np.array_equal(got[0], got[4])
             else:
                 for a, b in zip(got, ref):
-                    assert np.array_equal(a, b), n
+                    assert np.array_equal(a, b), (n, order)
     finally:
         api.set_slabs(1)
+        api.set_sweep_order(False)
 
 
 @pytest.mark.parametrize("prec", PRECS)
