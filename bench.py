@@ -31,11 +31,17 @@ sys.path.insert(0, ROOT)
 METRIC = "MCG site-updates/s and % HBM peak at 32^3x64; batched FP32 vs plain at equal R"
 LATTICES = [(32, 32, 32, 64), (24, 24, 24, 48), (20, 20, 20, 40), (16, 16, 16, 16)]
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of one site-update with FP32 links and an FP64 transform:
-# 8 links read and written + G(x) read and written.  In the two-row form (the
+# algorithmic bytes of one half-sweep site-update with FP32 links, keyed by
+# (two-row form, transform ring): the 8 links read and written, plus G(x) read
+# and written (FP64) or, with the ring, the site's g written once (two FP32
+# rows, 48 B; the fold kernel reads it later).  In the two-row form (the
 # default) a link is 6 complex FP32 (48 B) and G(x) 6 complex FP64 (96 B); as
 # full matrices 72 B and 144 B.
-BYTES_PER_SITE_UPDATE = {True: 8 * 48 * 2 + 2 * 96, False: 8 * 72 * 2 + 2 * 144}
+BYTES_PER_SITE_UPDATE = {(True, True): 8 * 48 * 2 + 48, (True, False): 8 * 48 * 2 + 2 * 96,
+                         (False, True): 8 * 72 * 2 + 48, (False, False): 8 * 72 * 2 + 2 * 144}
+# the fold kernel's bytes per site-update it folds, with GRING = 16 sweeps per fold:
+# g read once (48 B) + G(x) read and written once per 16 (2 * 96 / 16 in the two-row form)
+FOLD_BYTES_PER_SITE_UPDATE = {True: 48 + 2 * 96 / 16, False: 48 + 2 * 144 / 16}
 PMC_FILE = os.path.join(ROOT, "profiles", "halfsweep_pmc_32x32x32x64_fp32.json")
 
 
@@ -281,30 +287,23 @@ def one_step(api, fields, tol=1e-7, max_sweeps=5000):
     return out
 
 
-def roofline(api, torch, U, nsweeps=200, runs=5):
+def roofline(api, torch, U, nsweeps=192, runs=5):
     """Average duration of the half-sweep kernel at 32^3x64 (FP32 links, FP64
-    G), from HIP events on the stream the kernels are launched on (the
-    library launches on torch's current stream).  A call of api.sweeps also
-    converts W and G to and from the storage form; timing n + 20 and 20
-    sweeps and taking the difference leaves 2n half-sweep launches alone.
-    The median of `runs` such measurements after 10 warm-up sweeps."""
+    G), from HIP events that the library records on the stream the kernels
+    are launched on (torch's current stream) around each sweep's two
+    half-sweep launches (api.sweeps_timed): the folds of the transform ring
+    and the storage-form conversions fall outside.  The median over `runs`
+    calls of nsweeps sweeps each (a multiple of the ring's 16, so every call
+    has the same folds between its sweeps), after 16 warm-up sweeps."""
     W = U.clone()
     G = api.gauge_identity(U.L)
-    api.sweeps(W, G, 10)  # warm-up
+    api.sweeps(W, G, 16)  # warm-up
     torch.cuda.synchronize()
 
-    def timed(n):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        api.sweeps(W, G, n)
-        e1.record()
-        e1.synchronize()
-        return e0.elapsed_time(e1)
-
     import statistics
-    ms = statistics.median((timed(nsweeps + 20) - timed(20)) / (2 * nsweeps) for _ in range(runs))
-    two_row = api.get_two_row()
-    bps = BYTES_PER_SITE_UPDATE[two_row]
+    ms = statistics.median(api.sweeps_timed(W, G, nsweeps) / (2 * nsweeps) for _ in range(runs))
+    two_row, defer = api.get_two_row(), api.get_defer_g()
+    bps = BYTES_PER_SITE_UPDATE[(two_row, defer)]
     site_updates = api.volume(U.L) // 2
     achieved = site_updates * bps / (ms * 1e-3) / 1e9
     traffic = None
@@ -312,12 +311,25 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
         pmc = json.load(open(PMC_FILE))
         if pmc.get("kernel_source_hash") == kernel_source_hash():
             traffic = pmc.get("hbm_bytes_per_launch")
+    # the whole sweep loop, folds included: half-sweep and fold bytes over the plain sweeps' time
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    api.sweeps(W, G, nsweeps)
+    e1.record()
+    e1.synchronize()
+    loop_ms = e0.elapsed_time(e1) / (2 * nsweeps)
+    loop_bps = bps + (FOLD_BYTES_PER_SITE_UPDATE[two_row] if defer else 0)
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_halfsweep<float,%s> (one parity of 32^3x64, %s)" % (
+                kernel="k_halfsweep<float,%s> (one parity of 32^3x64, %s, %s)" % (
                     "two-row" if two_row else "full",
-                    "alternating tile order" if api.get_sweep_order() else "forward tile order"),
-                ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps)
+                    "alternating tile order" if api.get_sweep_order() else "forward tile order",
+                    "g to the transform ring" if defer else "G updated in place"),
+                ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps,
+                sweep_loop=dict(ms_per_half_sweep=round(loop_ms, 4), bytes_per_site_update=loop_bps,
+                                GBps=round(site_updates * loop_bps / (loop_ms * 1e-3) / 1e9, 1),
+                                note="api.sweeps end to end (conversions of W and G to and from the "
+                                     "storage form included), fold kernel bytes added"))
 
 
 def cpu_baseline(U64, target_s=15.0):
@@ -468,6 +480,8 @@ def main():
                             links="fp32", gauge="fp64", reductions="fp64", half_sweep_variant=best,
                             sweep_order="odd half-sweeps in reverse tile order" if api.get_sweep_order()
                             else "forward",
+                            transform="per-half-sweep g in a ring, folded into G every 16 sweeps"
+                            if api.get_defer_g() else "G updated in every half-sweep",
                             per_field=[dict(L=x["L"], sweeps_smeared=x["sweeps_smeared"], sweeps=x["sweeps"],
                                             R_smeared=round(x["R_smeared"], 7), R=round(x["R"], 7),
                                             vortex_fraction=round(x["vortex_fraction"], 5))

@@ -187,6 +187,13 @@ mcg_status mcg_halfsweep(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t parit
  * scratch before the sweeps and back after them. */
 mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
                       void *stream);
+/* mcg_sweeps (n >= 1) that also returns in *ms_halfsweeps (host) the summed
+ * duration of the half-sweep launches alone, from HIP events recorded on
+ * `stream` before and after each sweep's two half-sweeps: the folds of the
+ * transform ring (MCG_OPT_DEFER_G) and the storage-form conversions fall
+ * outside.  Synchronises the stream. */
+mcg_status mcg_sweeps_timed(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
+                            double *ms_halfsweeps, void *stream);
 /* Fix U to MCG.  G holds the start transform on entry (mcg_gauge_identity for
  * plain fixing; the smeared field's transform for the preconditioned re-fix)
  * and the total transform on exit; U is not modified.  The working field
@@ -264,6 +271,16 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * of one parity are independent and the reduction partials belong to tiles,
  * not to the launch order. */
 #define MCG_OPT_ORDER 8
+/* MCG_OPT_DEFER_G (0/1, default 1): with FP32 links, mcg_fix, mcg_fix_batch
+ * and mcg_sweeps let each half-sweep write its per-site g (two rows, FP32)
+ * into a ring of 16 sweeps instead of reading and writing the FP64
+ * transform, and fold the ring into G (one g at a time, in FP64, the same
+ * products in the same order) before each re-unitarisation, when the ring
+ * is full and at the end: 48 bytes per site-update instead of 192 (two-row
+ * form).  Results are bit-identical to 0.  Costs 768 * L0*L1*L2*L3 bytes of
+ * context scratch per field (32 slots of 48 bytes per site of one parity);
+ * FP64 fixes always update G in place. */
+#define MCG_OPT_DEFER_G 9
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,
  * vortex_field, wilson_loops, smear_mcg_backward) first checks them and

@@ -20,6 +20,7 @@ MCG_OPT_CHECK = 5
 MCG_OPT_SCRATCH_LIMIT_MIB = 6
 MCG_OPT_EXACT = 7
 MCG_OPT_ORDER = 8
+MCG_OPT_DEFER_G = 9
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 
@@ -73,6 +74,8 @@ SIGNATURES = {
     "mcg_theta": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_double), _P]),
     "mcg_halfsweep": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.c_int32, C.c_double, _P]),
     "mcg_sweeps": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.c_int32, C.c_double, _P]),
+    "mcg_sweeps_timed": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.c_int32, C.c_double,
+                              C.POINTER(C.c_double), _P]),
     "mcg_fix": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.POINTER(FixOpts),
                      C.POINTER(FixResult), _P]),
     "mcg_fix_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(Gauge),

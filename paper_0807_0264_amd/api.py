@@ -253,6 +253,18 @@ def sweeps(W, G, n, omega=1.7):
     _check(A.load().mcg_sweeps(ctx, C.byref(f), C.byref(g), int(n), float(omega), _stream()), ctx)
 
 
+def sweeps_timed(W, G, n, omega=1.7):
+    """sweeps() that returns the summed duration (ms) of the half-sweep
+    launches alone, timed with HIP events on the launch stream (the ring folds
+    and form conversions excluded).  Synchronises."""
+    ctx = context(W.data.device.index)
+    f, g = W.abi(), G.abi()
+    ms = C.c_double()
+    _check(A.load().mcg_sweeps_timed(ctx, C.byref(f), C.byref(g), int(n), float(omega), C.byref(ms), _stream()),
+           ctx)
+    return ms.value
+
+
 def _opts(tol, max_sweeps, omega, reunit_every, start_sweep, check_every, traj):
     o = A.FixOpts()
     o.tol = float(tol)
@@ -407,6 +419,20 @@ def set_sweep_order(alternate, device=None):
     order, starting where the even half-sweep ended (bit-identical results)."""
     ctx = context(device)
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_ORDER, 1 if alternate else 0), ctx)
+
+
+def set_defer_g(on, device=None):
+    """FP32 fixes and raw sweeps: keep each half-sweep's transform in a ring
+    and fold it into G later (bit-identical, fewer bytes per site-update)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_DEFER_G, 1 if on else 0), ctx)
+
+
+def get_defer_g(device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_DEFER_G, C.byref(v)), ctx)
+    return bool(v.value)
 
 
 def get_sweep_order(device=None):

@@ -286,6 +286,7 @@ struct Gauge {
 #pragma unroll
     for (int k = 0; k < 9; k++) st_plane(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
   }
+  __device__ __forceinline__ M3<double> load_fixed(int par, int h) const { return load(par, h); }
 };
 
 // Make the compiler treat the first two rows of m as freshly produced, so a
@@ -347,6 +348,52 @@ template <typename T> struct Links12 {
   }
 };
 
+// ------------------------------------------- transform updates in fixed FP64
+// G <- g G written with explicit fused multiply-adds in a fixed order, and the
+// two-row reconstruction likewise: the compiler contracts plain products into
+// FMAs as it sees fit in each kernel, so two kernels doing "the same" product
+// can differ in the last bit; these give the same bits wherever they are inlined.
+__device__ __forceinline__ cx<double> dot3_fma(cx<double> a0, cx<double> b0, cx<double> a1, cx<double> b1,
+                                               cx<double> a2, cx<double> b2) {
+  double re = a0.re * b0.re, im = a0.re * b0.im;
+  re = fma(-a0.im, b0.im, re);
+  im = fma(a0.im, b0.re, im);
+  re = fma(a1.re, b1.re, re);
+  re = fma(-a1.im, b1.im, re);
+  im = fma(a1.re, b1.im, im);
+  im = fma(a1.im, b1.re, im);
+  re = fma(a2.re, b2.re, re);
+  re = fma(-a2.im, b2.im, re);
+  im = fma(a2.re, b2.im, im);
+  im = fma(a2.im, b2.re, im);
+  return cx<double>{re, im};
+}
+__device__ __forceinline__ M3<double> mul_fixed(const M3<double> &a, const M3<double> &b) {
+  M3<double> c;
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3_fma(a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
+  return c;
+}
+// conj(x y - z w), the product terms fused in a fixed order
+__device__ __forceinline__ cx<double> cross_fma(cx<double> x, cx<double> y, cx<double> z, cx<double> w) {
+  double re = x.re * y.re, im = x.re * y.im;
+  re = fma(-x.im, y.im, re);
+  im = fma(x.im, y.re, im);
+  re = fma(-z.re, w.re, re);
+  re = fma(z.im, w.im, re);
+  im = fma(-z.re, w.im, im);
+  im = fma(-z.im, w.re, im);
+  return cx<double>{re, -im};
+}
+__device__ __forceinline__ void third_row_fixed(M3<double> &m) {
+  m.e[6] = cross_fma(m.e[1], m.e[5], m.e[2], m.e[4]);
+  m.e[7] = cross_fma(m.e[2], m.e[3], m.e[0], m.e[5]);
+  m.e[8] = cross_fma(m.e[0], m.e[4], m.e[1], m.e[3]);
+}
+
 // complex element (par, k < 6, h) at (par*6 + k)*Vh + h
 struct Gauge12 {
   double2 *p;
@@ -355,6 +402,11 @@ struct Gauge12 {
     return (unsigned)(par * 6 * Vh + h) * (unsigned)sizeof(double2);
   }
   __device__ __forceinline__ M3<double> load(int par, int h) const {
+    M3<double> m = load_rows(par, h);
+    third_row(m);
+    return m;
+  }
+  __device__ __forceinline__ M3<double> load_rows(int par, int h) const {
     const unsigned o = off(par, h);
     M3<double> m;
 #pragma unroll
@@ -362,7 +414,12 @@ struct Gauge12 {
       const double2 v = ld_plane(p + (size_t)k * Vh, o);
       m.e[k] = cx<double>{v.x, v.y};
     }
-    third_row(m);
+    return m;
+  }
+  // load with row 2 rebuilt by third_row_fixed (for transform updates)
+  __device__ __forceinline__ M3<double> load_fixed(int par, int h) const {
+    M3<double> m = load_rows(par, h);
+    third_row_fixed(m);
     return m;
   }
   __device__ __forceinline__ void store(int par, int h, const M3<double> &m) const {
@@ -429,16 +486,16 @@ template <int BS> __device__ __forceinline__ double block_min(double v) {
 }
 // Fixed-order sum of n partials by one block: thread t adds t, t+BS, ...
 // in order, then block_sum.  Result valid in thread 0.
-template <int BS> __device__ __forceinline__ double sum_partials(const double *p, int n) {
+template <int BS, int NL = 8> __device__ __forceinline__ double sum_partials(const double *p, int n) {
   double s = 0.0;
   int i = threadIdx.x;
-  // eight loads in flight per step; the additions keep the order i, i+BS, i+2BS, ...
-  for (; i + 7 * BS < n; i += 8 * BS) {
-    double v[8];
+  // NL loads in flight per step; the additions keep the order i, i+BS, i+2BS, ...
+  for (; i + (NL - 1) * BS < n; i += NL * BS) {
+    double v[NL];
 #pragma unroll
-    for (int k = 0; k < 8; k++) v[k] = p[i + k * BS];
+    for (int k = 0; k < NL; k++) v[k] = p[i + k * BS];
 #pragma unroll
-    for (int k = 0; k < 8; k++) s += v[k];
+    for (int k = 0; k < NL; k++) s += v[k];
   }
   for (; i < n; i += BS) s += p[i];
   return block_sum<BS>(s);

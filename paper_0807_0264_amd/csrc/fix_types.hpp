@@ -24,6 +24,7 @@ struct FixState {
   int32_t status;  // 0 converged, 1 not converged
   int32_t stop_every;   // the stop test only after sweeps whose global number is a multiple of it
   int32_t start_sweep;  // global number of the sweep before this call's first
+  int32_t kfold;        // sweeps whose transforms have been folded into G (k - kfold still in the ring)
 };
 
 constexpr int MAX_SLABS = 16;
@@ -46,6 +47,9 @@ template <typename T> struct LatDesc {
   double *part;    // npart = nblk * BS / 64 partial sums, one per 64-site wavefront
   int npart;
   double *traj;    // device copy of the R trajectory (max_k + 1) or null
+  // ring of per-half-sweep transforms (FP32 fields) or null: slot q holds rows 0 and 1 of the g of
+  // every site of parity q & 1, complex element (q, k < 6, h) at (q*6 + k)*Vh + h
+  V2<T> *gring;
 };
 
 }  // namespace mcg

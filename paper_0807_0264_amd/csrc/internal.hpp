@@ -17,10 +17,14 @@ inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 2
 template <typename T>
 // slab < 0: the whole of every field (blocks = total); slab >= 0: that slab's chunks (blocks = their total)
 // hits > 1 (re-linearisation hits) or exact (exact subgroup maximisation) requires variant 2
-// (256-thread blocks); rev: tiles in reverse grid order (same results, other visiting order)
+// (256-thread blocks); rev: tiles in reverse grid order (same results, other visiting order);
+// gslot >= 0: g goes to that slot of each field's transform ring instead of into G (k_fold)
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0,
-                            int rev = 0);
+                            int rev = 0, int gslot = -1);
+// fold the ring's transforms into G (nfix: the count for fields without a FixState)
+template <typename T>
+hipError_t launch_fold(int bs, bool c12, const void *D, int B, int blocks, int nfix, hipStream_t s);
 template <typename T>
 hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, bool gated, hipStream_t s);
 template <typename T>
@@ -32,7 +36,9 @@ template <typename T> hipError_t launch_book(const void *D, int B, int what, hip
 template <typename T>
 hipError_t launch_links_form(const Geom &g, const void *src, void *dst, bool to12, hipStream_t s);
 hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool to12, hipStream_t s);
-enum { BOOK_INIT = 0, BOOK_RESET = 1, BOOK_CHECK = 2, BOOK_FINAL = 3, BOOK_THETA = 4 };
+enum { BOOK_INIT = 0, BOOK_RESET = 1, BOOK_CHECK = 2, BOOK_FINAL = 3, BOOK_THETA = 4, BOOK_FOLD = 5 };
+// sweeps whose transforms an FP32 fix keeps in its ring before folding them into G
+constexpr int GRING_SWEEPS = 16;
 
 // k_field.hip -- layout conversion and whole-field measurements
 template <typename Tin, typename Tout>

@@ -26,13 +26,14 @@ namespace mcg {
 // c12: working field and transform stored as two rows
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
-                            bool withR, bool gated, hipStream_t s, int slab, int hits, int exact, int rev) {
+                            bool withR, bool gated, hipStream_t s, int slab, int hits, int exact, int rev,
+                            int gslot) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
   if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
 #define MCG_HM(WR, C, E) \
-  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, hits)
+  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, hits)
     if (exact) {
       if (c12) {
         if (withR) MCG_HM(true, true, true); else MCG_HM(false, true, true);
@@ -50,7 +51,7 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
     return hipGetLastError();
   }
 #define MCG_HS(WR, OCC, C)                                                                         \
-  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev)))
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot)))
   if (c12) {
     if (variant / 3 == 0) {
       if (withR) { MCG_HS(true, 1, true); } else { MCG_HS(false, 1, true); }
@@ -75,6 +76,17 @@ hipError_t launch_rederive(int bs, bool c12, const void *D, int B, int blocks, b
     MCG_BS_SWITCH(bs, (k_rederive<T, BS, true><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
   } else {
     MCG_BS_SWITCH(bs, (k_rederive<T, BS, false><<<blocks, BS, 0, s>>>(dd, B, gated ? 1 : 0)));
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fold(int bs, bool c12, const void *D, int B, int blocks, int nfix, hipStream_t s) {
+  const LatDesc<T> *dd = (const LatDesc<T> *)D;
+  if (c12) {
+    MCG_BS_SWITCH(bs, (k_fold<T, BS, true><<<blocks, BS, 0, s>>>(dd, B, nfix)));
+  } else {
+    MCG_BS_SWITCH(bs, (k_fold<T, BS, false><<<blocks, BS, 0, s>>>(dd, B, nfix)));
   }
   return hipGetLastError();
 }
@@ -121,7 +133,8 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t, int, int, int, int);                          \
+                                          hipStream_t, int, int, int, int, int);                     \
+  template hipError_t launch_fold<T>(int, bool, const void *, int, int, int, hipStream_t);            \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \
   template hipError_t launch_theta<T>(int, bool, const void *, int, int, hipStream_t);                \

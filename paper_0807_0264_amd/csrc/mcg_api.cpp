@@ -34,7 +34,7 @@ struct mcg_ctx {
   hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
   DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part, w12, g12;
   DevBuf line_a, line_b, wl_part, wl_res;  // Wilson loops: line fields, partial sums, results
-  std::vector<DevBuf> W, G12, fpart, traj;
+  std::vector<DevBuf> W, G12, fpart, traj, gring;
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
@@ -42,6 +42,7 @@ struct mcg_ctx {
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
   int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order (MCG_OPT_ORDER)
+  bool defer_g = true;  // FP32 fixes keep each half-sweep's g in a ring, folded into G later (MCG_OPT_DEFER_G)
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
   size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
   size_t scratch_used = 0;
@@ -164,6 +165,8 @@ size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
   const size_t V = (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3];
   return V * (c12 ? 6 : 9) * 2 * sizeof(double);
 }
+// the transform ring of an FP32 fix: 2 * GRING_SWEEPS slots of Vh two-row FP32 matrices
+size_t gring_bytes(const Geom &g) { return (size_t)2 * GRING_SWEEPS * 6 * g.Vh * sizeof(V2<float>); }
 
 // ------------------------------------------------------------ fixing driver
 // Largest |(M M^dag - 1)_ij| over U's links (and G's matrices when G is given), NaN as inf; host
@@ -246,12 +249,31 @@ template <typename T> struct FixRun {
   int hits = 1;
   int exact = 0;
   int order = 0;
+  // Deferred transform: with C > 0 every half-sweep writes its g into ring slot
+  // 2 * since_fold + parity instead of updating G, and fold() applies the ring to G before
+  // anything reads G (re-unitarisation, the end of the call) and whenever C sweeps are in it.
+  int C = 0;
+  int since_fold = 0;
+  bool stateful = true;  // fields carry a FixState (the fold count comes from it)
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
     if (blocks > 0)
       HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact,
-                                 order && par == 1));
+                                 order && par == 1, C ? 2 * since_fold + par : -1));
+    return MCG_OK;
+  }
+  // Launched whatever since_fold says on the host: a field's own count decides what is folded,
+  // so a captured block that starts with a fold is right on every replay.
+  mcg_status fold() {
+    if (!C) return MCG_OK;
+    HIPCHK(launch_fold<T>(bs, c12, dD, B, total_blocks, since_fold, s));
+    if (stateful) HIPCHK(launch_book<T>(dD, B, BOOK_FOLD, s));
+    since_fold = 0;
+    return MCG_OK;
+  }
+  mcg_status advance() {
+    if (C && ++since_fold == C) return fold();
     return MCG_OK;
   }
   // Even then odd half-sweep.  Slab by slab (n > 1), in the order E0 E1 [E(k) O(k-1)] for
@@ -271,15 +293,16 @@ template <typename T> struct FixRun {
     return MCG_OK;
   }
   mcg_status sweep(bool reunit_first) {
+    mcg_status st;
     if (reunit_first) {
+      if ((st = fold())) return st;
       HIPCHK(launch_reunit<T>(bs, c12, dD, B, total_blocks, true, s));
       HIPCHK(launch_rederive<T>(bs, c12, dD, B, total_blocks, true, s));
       HIPCHK(launch_book<T>(dD, B, BOOK_RESET, s));
     }
-    mcg_status st;
     if ((st = halfsweeps(true))) return st;
     HIPCHK(launch_book<T>(dD, B, BOOK_CHECK, s));
-    return MCG_OK;
+    return advance();
   }
 };
 
@@ -319,7 +342,9 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     ctx->G12.resize(B);
     ctx->fpart.resize(B);
     ctx->traj.resize(B);
+    ctx->gring.resize(B);
   }
+  const bool ring = prec == MCG_F32 && ctx->defer_g;
   mcg_status st;
   if ((st = ensure(ctx, ctx->states, sizeof(FixState) * B))) return st;
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>) * B))) return st;
@@ -333,6 +358,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12)))) return st;
     if (c12 && (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, true)))) return st;
     if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb * (bs / 64)))) return st;
+    if (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(g)))) return st;
     const bool want_traj = opts[b].traj != nullptr;
     if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
     LatDesc<T> d;
@@ -346,6 +372,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     d.part = (double *)ctx->fpart[b].p;
     d.npart = nb * (bs / 64);
     d.traj = want_traj ? (double *)ctx->traj[b].p : nullptr;
+    d.gring = ring ? (V2<T> *)ctx->gring[b].p : nullptr;
     hD[b] = d;
     FixState f;
     memset(&f, 0, sizeof f);
@@ -361,6 +388,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
+  run.C = ring ? GRING_SWEEPS : 0;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -435,6 +463,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
       (void)hipGraphExecDestroy(exec);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(ctx, MCG_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+      run.since_fold = cap.since_fold;  // every replay leaves the ring as the captured block did
     }
     while (!done && issued < kmax) {
       ++issued;
@@ -443,6 +472,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     }
   }
   // final re-unitarisation, R and the stationarity residual
+  if ((st = run.fold())) return st;
   HIPCHK(launch_reunit<T>(bs, c12, run.dD, B, total, false, s));
   HIPCHK(launch_rederive<T>(bs, c12, run.dD, B, total, false, s));
   HIPCHK(launch_book<T>(run.dD, B, BOOK_FINAL, s));
@@ -808,10 +838,11 @@ mcg_status mcg_theta(mcg_ctx *ctx, const mcg_field *W, double *theta, void *stre
 // parity >= 0: one half-sweep of that parity on the caller's (full-form)
 // fields.  parity < 0: n sweeps (0, 1, 0, 1, ...) in the context's storage
 // form; in the two-row form W and G are converted into context scratch,
-// swept, and converted back.
+// swept, and converted back.  ms: the summed duration of the half-sweep
+// launches alone (HIP events around each sweep's pair; synchronises).
 template <typename T>
 static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int parity, double omega,
-                                 hipStream_t s, int n = 1) {
+                                 hipStream_t s, int n = 1, double *ms = nullptr) {
   const Geom g = geom_of(W->d);
   const bool c12 = parity < 0 && ctx->c12;
   const int variant = (ctx->hits > 1 || ctx->exact) ? 2 : ctx->variant[W->prec][c12],
@@ -822,10 +853,16 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   if (c12 && ((st = ensure(ctx, ctx->w12, work_field_bytes(W->d, W->prec, true))) ||
               (st = ensure(ctx, ctx->g12, gauge_form_bytes(W->d, true)))))
     return st;
+  const bool ring = parity < 0 && W->prec == MCG_F32 && ctx->defer_g;
+  if (ring) {
+    if (ctx->gring.empty()) ctx->gring.resize(1);
+    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g)))) return st;
+  }
   // the pinned staging area may still feed an earlier copy on this stream
   HIPCHK(hipStreamSynchronize(s));
   LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
   memset(hD, 0, sizeof(LatDesc<T>));
+  hD->gring = ring ? (V2<T> *)ctx->gring[0].p : nullptr;
   hD->g = g;
   hD->nblk = nb;
   hD->nslab = 1;
@@ -836,6 +873,8 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
+  run.C = ring ? GRING_SWEEPS : 0;
+  run.stateful = false;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
@@ -847,8 +886,35 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
     HIPCHK(launch_links_form<T>(g, W->ptr, ctx->w12.p, true, s));
     HIPCHK(launch_gauge_form(g, G->ptr, (double *)ctx->g12.p, true, s));
   }
-  for (int k = 0; k < n; k++)
-    if ((st = run.halfsweeps(false))) return st;
+  if (!ms) {
+    for (int k = 0; k < n; k++)
+      if ((st = run.halfsweeps(false)) || (st = run.advance())) return st;
+  } else {
+    std::vector<hipEvent_t> ev((size_t)2 * n, nullptr);
+    hipError_t e = hipSuccess;
+    st = MCG_OK;
+    for (int k = 0; k < n && e == hipSuccess && st == MCG_OK; k++) {
+      e = hipEventCreate(&ev[2 * k]);
+      if (e == hipSuccess) e = hipEventCreate(&ev[2 * k + 1]);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s);
+      if (e == hipSuccess) st = run.halfsweeps(false);
+      if (e == hipSuccess && st == MCG_OK) e = hipEventRecord(ev[2 * k + 1], s);
+      if (e == hipSuccess && st == MCG_OK) st = run.advance();
+    }
+    if (e == hipSuccess && st == MCG_OK) e = hipEventSynchronize(ev[2 * n - 1]);
+    double total = 0.0;
+    for (int k = 0; k < n && e == hipSuccess && st == MCG_OK; k++) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+      total += t;
+    }
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ctx, MCG_EHIP, "timing events: %s", hipGetErrorString(e));
+    *ms = total;
+  }
+  if ((st = run.fold())) return st;
   if (c12) {
     HIPCHK(launch_links_form<T>(g, ctx->w12.p, W->ptr, false, s));
     HIPCHK(launch_gauge_form(g, (const double *)ctx->g12.p, G->ptr, false, s));
@@ -883,6 +949,12 @@ static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best,
   if (c12 && ((st = ensure(ctx, ctx->w12, work_field_bytes(U->d, U->prec, true))) ||
               (st = ensure(ctx, ctx->g12, gauge_form_bytes(U->d, true)))))
     return st;
+  // time the half-sweep the fixes run: with the transform ring (FP32) g goes to ring slots 0 and 1
+  const bool ring = U->prec == MCG_F32 && ctx->defer_g;
+  if (ring) {
+    if (ctx->gring.empty()) ctx->gring.resize(1);
+    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g)))) return st;
+  }
   HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
   if (c12) {
     HIPCHK(launch_links_form<T>(g, U->ptr, ctx->w12.p, true, s));
@@ -905,16 +977,17 @@ static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best,
     hD->nblk = nb;
     hD->W = c12 ? (V2<T> *)ctx->w12.p : (V2<T> *)ctx->tmpfield.p;
     hD->G = c12 ? (double2 *)ctx->g12.p : (double2 *)ctx->grad_a.p;
+    hD->gring = ring ? (V2<T> *)ctx->gring[0].p : nullptr;
     hipError_t e = hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (int k = 0; k < 4 && e == hipSuccess; k++)
       e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s, -1, 1, 0,
-                              ctx->order && (k & 1));
+                              ctx->order && (k & 1), ring ? (k & 1) : -1);
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     const int reps = 8;
     for (int k = 0; k < reps && e == hipSuccess; k++)
       e = launch_halfsweep<T>(v, c12, ctx->desc.p, 1, nb, k & 1, 1.7, false, false, s, -1, 1, 0,
-                              ctx->order && (k & 1));
+                              ctx->order && (k & 1), ring ? (k & 1) : -1);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
@@ -986,6 +1059,11 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->order = value;
     return MCG_OK;
   }
+  if (option == MCG_OPT_DEFER_G) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_DEFER_G takes 0 or 1");
+    ctx->defer_g = value != 0;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_CHECK) {
     if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_CHECK takes 0 or 1");
     ctx->check = value != 0;
@@ -1036,6 +1114,10 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
     *value = ctx->order;
     return MCG_OK;
   }
+  if (option == MCG_OPT_DEFER_G) {
+    *value = ctx->defer_g ? 1 : 0;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {
     *value = (int32_t)(ctx->scratch_limit >> 20);
     return MCG_OK;
@@ -1045,6 +1127,19 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
     return MCG_OK;
   }
   return fail(ctx, MCG_EINVAL, "unknown option %d", option);
+}
+
+mcg_status mcg_sweeps_timed(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
+                            double *ms_halfsweeps, void *stream) {
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, W, "W")) || (st = check_gauge(ctx, G, W->d, "G"))) return st;
+  if (n < 1) return fail(ctx, MCG_EINVAL, "n < 1");
+  if (!ms_halfsweeps) return fail(ctx, MCG_EINVAL, "NULL output");
+  if (!(omega >= 0.0 && omega <= 2.0)) return fail(ctx, MCG_EINVAL, "omega must lie in [0, 2]");
+  return W->prec == MCG_F64
+             ? halfsweep_impl<double>(ctx, W, G, -1, omega, (hipStream_t)stream, n, ms_halfsweeps)
+             : halfsweep_impl<float>(ctx, W, G, -1, omega, (hipStream_t)stream, n, ms_halfsweeps);
 }
 
 mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega, void *stream) {

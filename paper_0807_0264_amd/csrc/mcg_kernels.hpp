@@ -290,7 +290,8 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // sum_k |tr(s g M_k)|^2 over its subgroup exactly (then over-relaxes), `hits` rounds of three.
 template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
-                                                       T omega, int gated, int slab, int rev, int hits = 1) {
+                                                       T omega, int gated, int slab, int rev, int gslot,
+                                                       int hits = 1) {
   using WS = typename FixStore<T, C12>::W;
   using GS = typename FixStore<T, C12>::G;
   int lb;
@@ -394,7 +395,23 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       W.store_off(mu, ob[mu], bn);
       if (WR) r += tr2(bn);
     }
-    G.store(par, h, mul(m_cvt<double>(g), G.load(par, h)));
+    if (gslot >= 0) {
+      // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold)
+      const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        V2<T> v;
+        v.x = g.e[k].re;
+        v.y = g.e[k].im;
+        st_plane(d.gring + ((size_t)gslot * 6 + k) * d.g.Vh, o, v);
+      }
+    } else {
+      M3<double> gd = m_cvt<double>(g);
+      // FP32 g: row 2 rebuilt in FP64 from rows 0 and 1; the same fixed arithmetic as k_fold, so
+      // that updating G here and folding the ring later give the same bits
+      if constexpr (sizeof(T) == 4) third_row_fixed(gd);
+      G.store(par, h, mul_fixed(gd, G.load_fixed(par, h)));
+    }
   }
   if (WR) {
     const double s = wave_sum(r);
@@ -433,6 +450,38 @@ __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ 
   }
   const double s = wave_sum(r);
   if ((threadIdx.x & 63) == 0) d.part[((int)blockIdx.x - d.blk0) * (BS / 64) + (threadIdx.x >> 6)] = s;
+}
+
+// G <- g_{n-1} ... g_1 g_0 G for the transforms g_j that the half-sweeps of each parity left in
+// the ring (slot 2j + parity, rows 0 and 1; row 2 rebuilt in FP64), one g at a time and in the
+// storage form of G after each product, so the result is that of updating G in every half-sweep.
+// n = the sweeps the field ran since its last fold (its FixState), or nfix for a field without one.
+// Not gated: a field that has stopped still folds the sweeps it ran.
+template <typename T, int BS, bool C12>
+__global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, int B, int nfix) {
+  using GS = typename FixStore<T, C12>::G;
+  const int b = find_field(D, B);
+  const LatDesc<T> d = D[b];
+  const int n = d.st ? d.st->k - d.st->kfold : nfix;
+  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  if (h >= d.g.Vh || n <= 0 || !d.gring) return;
+  const GS G{d.G, d.g.Vh};
+  const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
+  for (int par = 0; par < 2; par++) {
+    M3<double> m = G.load_fixed(par, h);
+    for (int j = 0; j < n; j++) {
+      M3<double> gj;
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        const V2<T> v = ld_plane(d.gring + ((size_t)(2 * j + par) * 6 + k) * d.g.Vh, o);
+        gj.e[k] = cx<double>{(double)v.x, (double)v.y};
+      }
+      third_row_fixed(gj);
+      m = mul_fixed(gj, m);
+      if constexpr (C12) third_row_fixed(m);  // as a store and a reload of the two-row form would
+    }
+    G.store(par, h, m);
+  }
 }
 
 template <typename T, int BS, bool C12>
@@ -518,14 +567,20 @@ __global__ __launch_bounds__(256) void k_gauge_form(Geom g, const double2 *__res
 // ------------------------------------------------------ bookkeeping
 // One block per field (grid = B).  R is normalised as (1/(9 N_l)) sum |tr|^2, summed
 // over the per-wavefront partials in index order (independent of the block size).
-enum { BK_INIT = 0, BK_RESET = 1, BK_CHECK = 2, BK_FINAL = 3, BK_THETA = 4 };
+enum { BK_INIT = 0, BK_RESET = 1, BK_CHECK = 2, BK_FINAL = 3, BK_THETA = 4, BK_FOLD = 5 };
 
+// 32 loads in flight per thread: the 16384 wave partials of a 32^3x64 half-lattice arrive in two
+// round trips (the sum is latency-bound, once per sweep).
 template <typename T>
 __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, int what) {
   const LatDesc<T> d = D[blockIdx.x];
   FixState *st = d.st;
+  if (what == BK_FOLD) {  // after k_fold: every sweep run so far is in G
+    if (threadIdx.x == 0) st->kfold = st->k;
+    return;
+  }
   if ((what == BK_RESET || what == BK_CHECK) && st->done) return;
-  const double s = sum_partials<256>(d.part, d.npart);
+  const double s = sum_partials<256, 32>(d.part, d.npart);
   if (threadIdx.x != 0) return;
   const double R = s / (9.0 * (double)(4 * d.g.V));
   switch (what) {
@@ -534,6 +589,7 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
     st->R_last = R;
     st->dR = 0.0;
     st->k = 0;
+    st->kfold = 0;
     st->done = st->max_k <= 0 ? 1 : 0;
     st->status = 1;
     if (d.traj) d.traj[0] = R;

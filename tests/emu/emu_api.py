@@ -272,6 +272,10 @@ def set_sweep_order(alternate):
     check(lib().mcg_set_option(ctx(), 8, 1 if alternate else 0))
 
 
+def set_defer_g(on):
+    check(lib().mcg_set_option(ctx(), 9, 1 if on else 0))
+
+
 def set_check(on):
     check(lib().mcg_set_option(ctx(), 5, 1 if on else 0))
 

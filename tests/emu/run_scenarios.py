@@ -240,6 +240,36 @@ def scenario_variants(prec):
     E.set_two_row(True)
 
 
+def scenario_defer():
+    """FP32: the transform ring (each half-sweep's g folded into G later) gives
+    the bits of updating G in every half-sweep: a batch where one field stops
+    early, blocks replayed from a captured graph, more sweeps than the ring
+    holds, both storage forms, raw sweeps."""
+    prec = 1
+    L1, L2 = (4, 4, 4, 16), (4, 2, 2, 4)
+    U1, U2 = rounded(field(L1, 2090), prec), rounded(field(L2, 2091), prec)
+    G1 = S.haar_gauge(L1, S.sub_seed(2092))
+    for two_row in (True, False):
+        E.set_two_row(two_row)
+        got = []
+        for defer in (True, False):
+            E.set_defer_g(defer)
+            Gs = [E.gauge_identity(L2), E.gauge(G1)]
+            infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], Gs, [1e-5, -1.0], [70, 70],
+                                reunit_every=20, check_every=5)
+            G, info = E.fix(E.links(U1, prec), E.gauge(G1), tol=-1.0, max_sweeps=37, reunit_every=50,
+                            check_every=9)
+            W, Gd = E.links(U1, prec), E.gauge(G1)
+            E.sweeps(W, Gd, 35)
+            got.append([infos[0]["traj"], infos[1]["traj"], infos[0]["sweeps"], info["traj"], E.host_gauge(G),
+                        E.host_links(W), E.host_gauge(Gd)] + [E.host_gauge(x) for x in Gs])
+        check(got[0][2] < 70, f"the small field stops early ({got[0][2]} sweeps)")
+        for k, (a, b) in enumerate(zip(*got)):
+            check(np.array_equal(a, b), f"ring and in-place transform differ (item {k}, two_row={two_row})")
+    E.set_defer_g(True)
+    E.set_two_row(True)
+
+
 def expect_error(fn, status_word, what):
     try:
         fn()
@@ -297,7 +327,7 @@ def scenario_checks(prec):
 def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
     names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward",
-                             "loops", "slabs", "variants", "checks"]
+                             "loops", "slabs", "variants", "checks", "defer"]
     for name in names:
         if name == "batch":
             for prec in (0, 1):
@@ -307,6 +337,8 @@ def main():
         elif name == "checks":
             for prec in (0, 1):
                 scenario_checks(prec)
+        elif name == "defer":
+            scenario_defer()
         elif name == "variants":
             for prec in (0, 1):
                 scenario_variants(prec)

@@ -11,7 +11,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "emu")
 GROUPS = ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward", "loops",
-          "slabs", "variants", "checks"]
+          "slabs", "variants", "checks", "defer"]
 
 
 def _stale(lib, srcdirs):

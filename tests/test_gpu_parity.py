@@ -338,6 +338,40 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
         api.set_sweep_order(False)
 
 
+@pytest.mark.parametrize("two_row", [True, False])
+def test_transform_ring_is_bitwise(S, g, api, two_row):
+    """FP32: each half-sweep's g kept in the ring and folded into G later gives
+    the bits of updating G in every half-sweep: a batch where one field stops
+    early, blocks replayed from a captured graph, more sweeps than the ring
+    holds (16), a standalone fix and raw sweeps."""
+    prec = 1
+    L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
+    U1 = g.rounded(field(S, L1, 1055), prec)
+    U2 = g.rounded(field(S, L2, 1056), prec)
+    G1 = S.haar_gauge(L1, S.sub_seed(1057))
+    got = []
+    try:
+        api.set_two_row(two_row)
+        for defer in (True, False):
+            api.set_defer_g(defer)
+            assert api.get_defer_g() == defer
+            Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)],
+                                      [api.gauge_identity(L2), g.gauge(G1)], tol=[1e-4, -1.0],
+                                      max_sweeps=[130, 130], reunit_every=20, check_every=5, want_traj=True)
+            G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=37, reunit_every=50,
+                              check_every=9, want_traj=True)
+            W, Gd = g.links(U1, prec), g.gauge(G1)
+            api.sweeps(W, Gd, 35)
+            got.append([infos[0]["traj"], infos[1]["traj"], infos[0]["sweeps"], g.host_gauge(Gb[0]),
+                        g.host_gauge(Gb[1]), info["traj"], g.host_gauge(G), g.host_links(W), g.host_gauge(Gd)])
+    finally:
+        api.set_defer_g(True)
+        api.set_two_row(True)
+    assert got[0][2] < 130
+    for k, (a, b) in enumerate(zip(*got)):
+        assert np.array_equal(a, b), k
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 6, 6, 10)])
 def test_update_variants(S, O, g, api, L, prec):
