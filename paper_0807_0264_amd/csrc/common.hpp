@@ -227,6 +227,41 @@ template <typename V>
 __device__ __forceinline__ void st_plane(V *plane, unsigned byte_off, V v) {
   *(V *)((char *)plane + byte_off) = v;
 }
+// Streaming loads and stores (non-temporal hint) for data touched once: the
+// transform ring, written by a half-sweep and read back by the fold many
+// sweeps later, so it does not displace the links in the last-level cache.
+// The host build of these sources (the emulation) uses plain accesses.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef float mcg_f2v __attribute__((ext_vector_type(2)));
+typedef double mcg_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_plane_stream(const float2 *plane, unsigned byte_off) {
+  const mcg_f2v w = __builtin_nontemporal_load((const mcg_f2v *)((const char *)plane + byte_off));
+  return make_float2(w.x, w.y);
+}
+__device__ __forceinline__ double2 ld_plane_stream(const double2 *plane, unsigned byte_off) {
+  const mcg_d2v w = __builtin_nontemporal_load((const mcg_d2v *)((const char *)plane + byte_off));
+  return make_double2(w.x, w.y);
+}
+__device__ __forceinline__ void st_plane_stream(float2 *plane, unsigned byte_off, float2 v) {
+  mcg_f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, (mcg_f2v *)((char *)plane + byte_off));
+}
+__device__ __forceinline__ void st_plane_stream(double2 *plane, unsigned byte_off, double2 v) {
+  mcg_d2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, (mcg_d2v *)((char *)plane + byte_off));
+}
+#else
+template <typename V> __device__ __forceinline__ V ld_plane_stream(const V *plane, unsigned byte_off) {
+  return ld_plane(plane, byte_off);
+}
+template <typename V> __device__ __forceinline__ void st_plane_stream(V *plane, unsigned byte_off, V v) {
+  st_plane(plane, byte_off, v);
+}
+#endif
 
 // complex element (mu, par, k, h) at ((mu*2 + par)*9 + k)*Vh + h
 //   = (mu*18 + k)*Vh  [uniform]  +  par*9*Vh + h  [per lane]

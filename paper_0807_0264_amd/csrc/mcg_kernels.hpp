@@ -396,14 +396,15 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       if (WR) r += tr2(bn);
     }
     if (gslot >= 0) {
-      // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold)
+      // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold); streaming
+      // stores leave the last-level cache to the links that the next half-sweep reads
       const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
 #pragma unroll
       for (int k = 0; k < 6; k++) {
         V2<T> v;
         v.x = g.e[k].re;
         v.y = g.e[k].im;
-        st_plane(d.gring + ((size_t)gslot * 6 + k) * d.g.Vh, o, v);
+        st_plane_stream(d.gring + ((size_t)gslot * 6 + k) * d.g.Vh, o, v);
       }
     } else {
       M3<double> gd = m_cvt<double>(g);
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, i
       M3<double> gj;
 #pragma unroll
       for (int k = 0; k < 6; k++) {
-        const V2<T> v = ld_plane(d.gring + ((size_t)(2 * j + par) * 6 + k) * d.g.Vh, o);
+        const V2<T> v = ld_plane_stream(d.gring + ((size_t)(2 * j + par) * 6 + k) * d.g.Vh, o);
         gj.e[k] = cx<double>{(double)v.x, (double)v.y};
       }
       third_row_fixed(gj);
