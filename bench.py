@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # full matrices 72 B and 144 B.
 BYTES_PER_SITE_UPDATE = {(True, True): 8 * 48 * 2 + 48, (True, False): 8 * 48 * 2 + 2 * 96,
                          (False, True): 8 * 72 * 2 + 48, (False, False): 8 * 72 * 2 + 2 * 144}
-# the fold kernel's bytes per site-update it folds, with GRING = 16 sweeps per fold:
-# g read once (48 B) + G(x) read and written once per 16 (2 * 96 / 16 in the two-row form)
-FOLD_BYTES_PER_SITE_UPDATE = {True: 48 + 2 * 96 / 16, False: 48 + 2 * 144 / 16}
+# the fold kernel's bytes per site-update it folds, with 25 sweeps per fold (raw sweeps, and
+# fixes re-unitarising every 50): g read once (48 B) + G(x) read and written once per 25
+FOLD_BYTES_PER_SITE_UPDATE = {True: 48 + 2 * 96 / 25, False: 48 + 2 * 144 / 25}
 PMC_FILE = os.path.join(ROOT, "profiles", "halfsweep_pmc_32x32x32x64_fp32.json")
 
 
@@ -287,17 +287,17 @@ def one_step(api, fields, tol=1e-7, max_sweeps=5000):
     return out
 
 
-def roofline(api, torch, U, nsweeps=192, runs=5):
+def roofline(api, torch, U, nsweeps=200, runs=5):
     """Average duration of the half-sweep kernel at 32^3x64 (FP32 links, FP64
     G), from HIP events that the library records on the stream the kernels
     are launched on (torch's current stream) around each sweep's two
     half-sweep launches (api.sweeps_timed): the folds of the transform ring
     and the storage-form conversions fall outside.  The median over `runs`
-    calls of nsweeps sweeps each (a multiple of the ring's 16, so every call
-    has the same folds between its sweeps), after 16 warm-up sweeps."""
+    calls of nsweeps sweeps each (a multiple of the ring's 25, so every call
+    has the same folds between its sweeps), after 25 warm-up sweeps."""
     W = U.clone()
     G = api.gauge_identity(U.L)
-    api.sweeps(W, G, 16)  # warm-up
+    api.sweeps(W, G, 25)  # warm-up
     torch.cuda.synchronize()
 
     import statistics
@@ -480,7 +480,7 @@ def main():
                             links="fp32", gauge="fp64", reductions="fp64", half_sweep_variant=best,
                             sweep_order="odd half-sweeps in reverse tile order" if api.get_sweep_order()
                             else "forward",
-                            transform="per-half-sweep g in a ring, folded into G every 16 sweeps"
+                            transform="per-half-sweep g in a ring, folded into G every 25 sweeps"
                             if api.get_defer_g() else "G updated in every half-sweep",
                             per_field=[dict(L=x["L"], sweeps_smeared=x["sweeps_smeared"], sweeps=x["sweeps"],
                                             R_smeared=round(x["R_smeared"], 7), R=round(x["R"], 7),

@@ -273,13 +273,16 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
 #define MCG_OPT_ORDER 8
 /* MCG_OPT_DEFER_G (0/1, default 1): with FP32 links, mcg_fix, mcg_fix_batch
  * and mcg_sweeps let each half-sweep write its per-site g (two rows, FP32)
- * into a ring of 16 sweeps instead of reading and writing the FP64
+ * into a ring of at most 25 sweeps instead of reading and writing the FP64
  * transform, and fold the ring into G (one g at a time, in FP64, the same
  * products in the same order) before each re-unitarisation, when the ring
  * is full and at the end: 48 bytes per site-update instead of 192 (two-row
- * form).  Results are bit-identical to 0.  Costs 768 * L0*L1*L2*L3 bytes of
- * context scratch per field (32 slots of 48 bytes per site of one parity);
- * FP64 fixes always update G in place. */
+ * form).  The ring of a fix holds ceil(r / ceil(r / 25)) sweeps, r its
+ * reunit_every (25 for the default 50: folds after sweeps 25 and 50 of each
+ * block), that of mcg_sweeps 25.  Results are bit-identical to 0.  Costs
+ * 48 * C * L0*L1*L2*L3 bytes of context scratch per field for a ring of C
+ * sweeps (2C slots of 48 bytes per site of one parity; 1200 bytes per site at
+ * C = 25); FP64 fixes always update G in place. */
 #define MCG_OPT_DEFER_G 9
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,

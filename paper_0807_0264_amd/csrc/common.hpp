@@ -322,6 +322,22 @@ struct Gauge {
     for (int k = 0; k < 9; k++) st_plane(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
   }
   __device__ __forceinline__ M3<double> load_fixed(int par, int h) const { return load(par, h); }
+  // streaming forms (the ring fold: G is not touched again until the next fold)
+  __device__ __forceinline__ M3<double> load_fixed_stream(int par, int h) const {
+    const unsigned o = off(par, h);
+    M3<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+      const double2 v = ld_plane_stream(p + (size_t)k * Vh, o);
+      m.e[k] = cx<double>{v.x, v.y};
+    }
+    return m;
+  }
+  __device__ __forceinline__ void store_stream(int par, int h, const M3<double> &m) const {
+    const unsigned o = off(par, h);
+#pragma unroll
+    for (int k = 0; k < 9; k++) st_plane_stream(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
+  }
 };
 
 // Make the compiler treat the first two rows of m as freshly produced, so a
@@ -456,6 +472,23 @@ struct Gauge12 {
     M3<double> m = load_rows(par, h);
     third_row_fixed(m);
     return m;
+  }
+  // streaming forms (the ring fold: G is not touched again until the next fold)
+  __device__ __forceinline__ M3<double> load_fixed_stream(int par, int h) const {
+    const unsigned o = off(par, h);
+    M3<double> m;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const double2 v = ld_plane_stream(p + (size_t)k * Vh, o);
+      m.e[k] = cx<double>{v.x, v.y};
+    }
+    third_row_fixed(m);
+    return m;
+  }
+  __device__ __forceinline__ void store_stream(int par, int h, const M3<double> &m) const {
+    const unsigned o = off(par, h);
+#pragma unroll
+    for (int k = 0; k < 6; k++) st_plane_stream(p + (size_t)k * Vh, o, make_double2(m.e[k].re, m.e[k].im));
   }
   __device__ __forceinline__ void store(int par, int h, const M3<double> &m) const {
     const unsigned o = off(par, h);

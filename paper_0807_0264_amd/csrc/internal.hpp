@@ -37,8 +37,14 @@ template <typename T>
 hipError_t launch_links_form(const Geom &g, const void *src, void *dst, bool to12, hipStream_t s);
 hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool to12, hipStream_t s);
 enum { BOOK_INIT = 0, BOOK_RESET = 1, BOOK_CHECK = 2, BOOK_FINAL = 3, BOOK_THETA = 4, BOOK_FOLD = 5 };
-// sweeps whose transforms an FP32 fix keeps in its ring before folding them into G
-constexpr int GRING_SWEEPS = 16;
+// most sweeps whose transforms an FP32 fix keeps in its ring before folding them into G
+constexpr int GRING_SWEEPS = 25;
+// ring length of a fix that re-unitarises every `re` sweeps: the fewest folds per block of re
+// sweeps, spread evenly (re = 50: folds after sweeps 25 and 50 of each block)
+inline int gring_sweeps(int re) {
+  const int folds = (re + GRING_SWEEPS - 1) / GRING_SWEEPS;
+  return (re + folds - 1) / folds;
+}
 
 // k_field.hip -- layout conversion and whole-field measurements
 template <typename Tin, typename Tout>

@@ -165,8 +165,8 @@ size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
   const size_t V = (size_t)d.L[0] * d.L[1] * d.L[2] * d.L[3];
   return V * (c12 ? 6 : 9) * 2 * sizeof(double);
 }
-// the transform ring of an FP32 fix: 2 * GRING_SWEEPS slots of Vh two-row FP32 matrices
-size_t gring_bytes(const Geom &g) { return (size_t)2 * GRING_SWEEPS * 6 * g.Vh * sizeof(V2<float>); }
+// the transform ring of an FP32 fix holding C sweeps: 2C slots of Vh two-row FP32 matrices
+size_t gring_bytes(const Geom &g, int C) { return (size_t)2 * C * 6 * g.Vh * sizeof(V2<float>); }
 
 // ------------------------------------------------------------ fixing driver
 // Largest |(M M^dag - 1)_ij| over U's links (and G's matrices when G is given), NaN as inf; host
@@ -358,7 +358,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12)))) return st;
     if (c12 && (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, true)))) return st;
     if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb * (bs / 64)))) return st;
-    if (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(g)))) return st;
+    if (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(g, gring_sweeps(re))))) return st;
     const bool want_traj = opts[b].traj != nullptr;
     if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
     LatDesc<T> d;
@@ -388,7 +388,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
-  run.C = ring ? GRING_SWEEPS : 0;
+  run.C = ring ? gring_sweeps(re) : 0;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -856,7 +856,7 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   const bool ring = parity < 0 && W->prec == MCG_F32 && ctx->defer_g;
   if (ring) {
     if (ctx->gring.empty()) ctx->gring.resize(1);
-    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g)))) return st;
+    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g, GRING_SWEEPS)))) return st;
   }
   // the pinned staging area may still feed an earlier copy on this stream
   HIPCHK(hipStreamSynchronize(s));
@@ -953,7 +953,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, const mcg_field *U, int32_t *best,
   const bool ring = U->prec == MCG_F32 && ctx->defer_g;
   if (ring) {
     if (ctx->gring.empty()) ctx->gring.resize(1);
-    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g)))) return st;
+    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g, GRING_SWEEPS)))) return st;
   }
   HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
   if (c12) {

@@ -469,7 +469,7 @@ __global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, i
   const GS G{d.G, d.g.Vh};
   const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
   for (int par = 0; par < 2; par++) {
-    M3<double> m = G.load_fixed(par, h);
+    M3<double> m = G.load_fixed_stream(par, h);
     for (int j = 0; j < n; j++) {
       M3<double> gj;
 #pragma unroll
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, i
       m = mul_fixed(gj, m);
       if constexpr (C12) third_row_fixed(m);  // as a store and a reload of the two-row form would
     }
-    G.store(par, h, m);
+    G.store_stream(par, h, m);
   }
 }
 

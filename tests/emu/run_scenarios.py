@@ -256,7 +256,7 @@ def scenario_defer():
             E.set_defer_g(defer)
             Gs = [E.gauge_identity(L2), E.gauge(G1)]
             infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], Gs, [1e-5, -1.0], [70, 70],
-                                reunit_every=20, check_every=5)
+                                reunit_every=30, check_every=5)
             G, info = E.fix(E.links(U1, prec), E.gauge(G1), tol=-1.0, max_sweeps=37, reunit_every=50,
                             check_every=9)
             W, Gd = E.links(U1, prec), E.gauge(G1)

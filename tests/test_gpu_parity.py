@@ -342,8 +342,9 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
 def test_transform_ring_is_bitwise(S, g, api, two_row):
     """FP32: each half-sweep's g kept in the ring and folded into G later gives
     the bits of updating G in every half-sweep: a batch where one field stops
-    early, blocks replayed from a captured graph, more sweeps than the ring
-    holds (16), a standalone fix and raw sweeps."""
+    early, blocks of 30 sweeps replayed from a captured graph (ring of 15:
+    a fold inside each block and one at its start), a standalone fix (ring
+    of 25, 37 sweeps) and raw sweeps."""
     prec = 1
     L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
     U1 = g.rounded(field(S, L1, 1055), prec)
@@ -357,7 +358,7 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
             assert api.get_defer_g() == defer
             Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)],
                                       [api.gauge_identity(L2), g.gauge(G1)], tol=[1e-4, -1.0],
-                                      max_sweeps=[130, 130], reunit_every=20, check_every=5, want_traj=True)
+                                      max_sweeps=[130, 130], reunit_every=30, check_every=5, want_traj=True)
             G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=37, reunit_every=50,
                               check_every=9, want_traj=True)
             W, Gd = g.links(U1, prec), g.gauge(G1)
