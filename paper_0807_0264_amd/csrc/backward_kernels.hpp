@@ -211,6 +211,42 @@ template <> struct Path<3> {
   static constexpr int sgn[5] = {+1, +1, +1, -1, -1};
 };
 
+// The factor of step K of path W (K != J) joins the product before step J
+// (pre) or after it (post); the first factor of each side is taken as it is
+// (a product with the identity would cost a full 3x3 product: it cannot be
+// folded away, because of signed zeros).
+template <typename T, int K, int J>
+__device__ __forceinline__ void take_factor(M3<T> &pre, M3<T> &post, const M3<T> &f, bool dagger) {
+  if constexpr (K < J) {
+    if constexpr (K == 0) pre = dagger ? dag(f) : f;
+    else pre = dagger ? mul_nd(pre, f) : mul(pre, f);
+  } else {
+    if constexpr (K == J + 1) post = dagger ? dag(f) : f;
+    else post = dagger ? mul_nd(post, f) : mul(post, f);
+  }
+}
+
+// Walk path W from pos, step K onwards, collecting the factors of every step but J.
+template <typename T, int W, int J, int K>
+__device__ __forceinline__ void walk_path(const Geom &g, const Links<T> &L, int pos[4], int mu, int nu, int sg,
+                                          M3<T> &pre, M3<T> &post) {
+  if constexpr (K < Path<W>::n) {
+    constexpr int sym = Path<W>::sym[K], sgn = Path<W>::sgn[K];
+    const int d = sym ? nu : mu, s = sym ? sgn * sg : sgn;
+    int t[4];
+    if (s > 0) {
+      if constexpr (K != J) take_factor<T, K, J>(pre, post, L.at(g, pos, d), false);
+      moved(g, pos, d, +1, t);
+    } else {
+      moved(g, pos, d, -1, t);
+      if constexpr (K != J) take_factor<T, K, J>(pre, post, L.at(g, t, d), true);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) pos[q] = t[q];
+    walk_path<T, W, J, K + 1>(g, L, pos, mu, nu, sg, pre, post);
+  }
+}
+
 // Add to acc the terms of path W of C_mu(x) (over nu, sg) whose step J is the
 // link (y, lnu) given by coordinates y.
 template <typename T, int W, int J>
@@ -235,29 +271,14 @@ __device__ __forceinline__ void path_term(const Geom &g, const Links<T> &L, cons
     for (int q = 0; q < 4; q++) x[q] = t[q];
   }
   // walk from x: factors before and after step J
-  M3<T> pre = m_ident<T>(), post = m_ident<T>();
+  M3<T> pre, post;
   int pos[4] = {x[0], x[1], x[2], x[3]};
-#pragma unroll
-  for (int k = 0; k < P::n; k++) {
-    const int d = P::sym[k] ? nu : mu, s = P::sym[k] ? P::sgn[k] * sg : P::sgn[k];
-    int t[4];
-    if (s > 0) {
-      if (k != J) {
-        const M3<T> f = L.at(g, pos, d);
-        if (k < J) pre = mul(pre, f); else post = mul(post, f);
-      }
-      moved(g, pos, d, +1, t);
-    } else {
-      moved(g, pos, d, -1, t);
-      if (k != J) {
-        const M3<T> f = L.at(g, t, d);
-        if (k < J) pre = mul_nd(pre, f); else post = mul_nd(post, f);
-      }
-    }
-    for (int q = 0; q < 4; q++) pos[q] = t[q];
-  }
+  walk_path<T, W, J, 0>(g, L, pos, mu, nu, sg, pre, post);
   const M3<T> gc = GC.at(g, x, mu);
-  const M3<T> term = mul_nd(mul_dn(pre, gc), post);  // pre^dag gc post^dag
+  M3<T> term;  // pre^dag gc post^dag, an empty side being the identity
+  if constexpr (J == 0) term = mul_nd(gc, post);
+  else if constexpr (J == P::n - 1) term = mul_dn(pre, gc);
+  else term = mul_nd(mul_dn(pre, gc), post);
   if (sJ > 0) {
 #pragma unroll
     for (int k = 0; k < 9; k++) acc.e[k] = acc.e[k] + wt * term.e[k];
