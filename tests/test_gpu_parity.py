@@ -374,6 +374,29 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_sweeps_timed(S, g, api, prec):
+    """mcg_sweeps_timed leaves W and G exactly as mcg_sweeps does (ring folds
+    included for FP32) and returns the half-sweeps' own duration: positive and
+    within the wall time of the call."""
+    import time
+
+    import torch
+    L = (8, 8, 8, 32)
+    U = g.rounded(field(S, L, 1058), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1059))
+    W1, G1 = g.links(U, prec), g.gauge(G0)
+    api.sweeps(W1, G1, 30)
+    W2, G2 = g.links(U, prec), g.gauge(G0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = api.sweeps_timed(W2, G2, 30)
+    wall = 1000 * (time.perf_counter() - t0)
+    assert np.array_equal(g.host_links(W1), g.host_links(W2))
+    assert np.array_equal(g.host_gauge(G1), g.host_gauge(G2))
+    assert 0 < ms < wall
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 6, 6, 10)])
 def test_update_variants(S, O, g, api, L, prec):
     """Re-linearisation hits and the block-wise stop test against the oracle."""
