@@ -214,14 +214,21 @@ mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge 
 /* The half-sweep kernel has MCG_NUM_VARIANTS variants: variant v uses blocks
  * of {64, 128, 256}[v % 3] threads and targets 1 + v / 3 waves per SIMD.
  * mcg_autotune times every variant on a scratch copy of U (G = 1; U is not
- * modified) in the context's storage form, keeps the fastest for U's
+ * modified) in the context's storage form, in three interleaved rounds of 8
+ * half-sweeps each, keeps the variant with the smallest median for U's
  * precision and that form, and returns it (best_variant,
- * ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host).  The variant fixes the
+ * ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host: the medians).  The variant fixes the
  * block decomposition of every fixing kernel, hence the order of the FP64
  * partial sums: results at one variant are deterministic. */
 #define MCG_NUM_VARIANTS 6
 mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant,
                         double *ms_per_halfsweep, void *stream);
+/* mcg_autotune over a batch: every timed launch is one half-sweep over all B
+ * fields (U[0..B-1], one precision, host array of descriptors), as
+ * mcg_fix_batch runs them; the choice is kept for that precision and storage
+ * form.  Uses the scratch that mcg_fix_batch on the same fields uses. */
+mcg_status mcg_autotune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, int32_t *best_variant,
+                              double *ms_per_halfsweep, void *stream);
 mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant);
 mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
 

@@ -94,6 +94,8 @@ SIGNATURES = {
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), _P]),
     "mcg_autotune": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
+    "mcg_autotune_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                _P]),
     "mcg_set_variant": (_S, [_CTX, C.c_int32, C.c_int32]),
     "mcg_get_variant": (_S, [_CTX, C.c_int32, C.POINTER(C.c_int32)]),
     "mcg_set_option": (_S, [_CTX, C.c_int32, C.c_int32]),

@@ -386,12 +386,26 @@ def smear_mcg_backward(U, rho, eps, n, Gstar, ckpt_every=5):
 
 
 def autotune(U):
-    """Time every half-sweep variant on a copy of U; keep and return the fastest."""
+    """Time every half-sweep variant on a copy of U; keep and return the fastest
+    (median of three interleaved rounds)."""
     ctx = context(U.data.device.index)
     f = U.abi()
     best = C.c_int32()
     ms = (C.c_double * A.MCG_NUM_VARIANTS)()
     _check(A.load().mcg_autotune(ctx, C.byref(f), C.byref(best), ms, _stream()), ctx)
+    return best.value, list(ms)
+
+
+def autotune_batch(Us):
+    """Time every half-sweep variant on copies of the fields Us (one
+    precision), each launch covering the whole batch as fix_batch runs it;
+    keep and return the fastest (median of three interleaved rounds)."""
+    ctx = context(Us[0].data.device.index)
+    B = len(Us)
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    best = C.c_int32()
+    ms = (C.c_double * A.MCG_NUM_VARIANTS)()
+    _check(A.load().mcg_autotune_batch(ctx, B, F, C.byref(best), ms, _stream()), ctx)
     return best.value, list(ms)
 
 

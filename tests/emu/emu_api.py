@@ -262,6 +262,21 @@ def set_variant(prec, v):
     check(lib().mcg_set_variant(ctx(), prec, v))
 
 
+def get_variant(prec):
+    v = C.c_int32()
+    check(lib().mcg_get_variant(ctx(), prec, C.byref(v)))
+    return v.value
+
+
+def autotune_batch(Us):
+    B = len(Us)
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    best = C.c_int32()
+    ms = (C.c_double * 6)()
+    check(lib().mcg_autotune_batch(ctx(), B, F, C.byref(best), ms, None))
+    return best.value, list(ms)
+
+
 def set_update_variant(hits, stop_every, exact=False):
     check(lib().mcg_set_option(ctx(), 3, hits))
     check(lib().mcg_set_option(ctx(), 4, stop_every))

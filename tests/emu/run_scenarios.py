@@ -127,6 +127,13 @@ def scenario_batch(prec):
                       reunit_every=3, check_every=2)
         check(ib["sweeps"] == infos[b]["sweeps"], "batch sweeps")
         check(ib["R"] == infos[b]["R"] and np.array_equal(ib["traj"], infos[b]["traj"]), "batch bits")
+    # the batched tuner: launches over the whole batch, its choice kept; the fields are not modified
+    Ws = [E.links(U, prec) for U in Us]
+    before = [E.host_links(W) for W in Ws]
+    best, ms = E.autotune_batch(Ws)
+    check(0 <= best < 6 and all(t > 0 for t in ms) and E.get_variant(prec) == best, f"autotune_batch {best}")
+    check(all(np.array_equal(a, E.host_links(W)) for a, W in zip(before, Ws)), "autotune leaves U alone")
+    E.set_variant(prec, 2)
 
 
 def scenario_planted():

@@ -290,6 +290,26 @@ def test_autotune_keeps_results_valid(S, g, api):
     assert np.abs(info["traj"] - info2["traj"]).max() < 1e-6
 
 
+def test_autotune_batch(S, g, api):
+    """The batched tuner times launches over the whole batch, keeps its
+    choice for the precision and storage form, and a batched fix afterwards
+    gives the bits of the same fix at a fixed variant (results do not depend
+    on the launch shape)."""
+    Ls = [(6, 6, 6, 10), (4, 4, 4, 4), (8, 8, 8, 16)]
+    Us = [g.rounded(field(S, L, 1034 + i), 1) for i, L in enumerate(Ls)]
+    try:
+        best, ms = api.autotune_batch([g.links(U, 1) for U in Us])
+        assert 0 <= best < 6 and all(t > 0 for t in ms)
+        assert api.get_variant(1) == best
+        _, a = api.fix_batch([g.links(U, 1) for U in Us], None, tol=-1.0, max_sweeps=12, want_traj=True)
+        api.set_variant(1, (best + 1) % 6)
+        _, b = api.fix_batch([g.links(U, 1) for U in Us], None, tol=-1.0, max_sweeps=12, want_traj=True)
+        for x, y in zip(a, b):
+            assert np.array_equal(x["traj"], y["traj"])
+    finally:
+        api.set_variant(1, 2)
+
+
 def test_synth_gpu_is_bitwise_cpu(S, g):
     for L, n in (((4, 4, 4, 4), 4), ((6, 4, 4, 8), 3)):
         a = S.heatbath_field(L, S.sub_seed(1040), 5.7, n)
