@@ -134,6 +134,7 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
         return int(d[0]) if len(d) else None
 
     best64, _ = api.autotune(U64)
+    best32, _ = api.autotune_batch([U] * ncopies)  # the batch the FP32 path fixes
     levels = []
     for n in (0, nsmear):
         runs = {}
@@ -168,7 +169,7 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
             not_converged=sum(x["status"] != 0 for x in a + b)))
     return dict(workload=f"{ncopies} Haar Gribov copies of one {'x'.join(map(str, L))} field, "
                          f"tol {tol}, all copies batched (FP32 links) vs one by one (FP64 links)",
-                fp64_variant=best64, levels=levels)
+                fp64_variant=best64, fp32_variant=best32, levels=levels)
 
 
 # Wilson loops of the static-potential measurement (Sec. III.B) on the 20^3x40

@@ -953,15 +953,21 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   }
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>) * B)) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>) * B)))
     return st;
-  // each field's working copy in the storage form and an identity transform, in the fix's scratch
+  // each field's working copy in the storage form and an identity transform, in the fix's scratch;
+  // every buffer is reserved before the first kernel is queued (a grown buffer is freed and
+  // reallocated, which must not happen under queued work)
+  size_t gfull = 0;
   for (int b = 0; b < B; b++) {
-    const Geom g = geom_of(U[b].d);
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12))) ||
         (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, c12))) ||
-        (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(g, 1)))))
+        (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(geom_of(U[b].d), 1)))))
       return st;
+    gfull = std::max(gfull, mcg_gauge_bytes(U[b].d));
+  }
+  if (c12 && (st = ensure(ctx, ctx->grad_a, gfull))) return st;
+  for (int b = 0; b < B; b++) {
+    const Geom g = geom_of(U[b].d);
     if (c12) {
-      if ((st = ensure(ctx, ctx->grad_a, mcg_gauge_bytes(U[b].d)))) return st;
       HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
       HIPCHK(launch_gauge_form(g, (const double *)ctx->grad_a.p, (double *)ctx->G12[b].p, true, s));
       HIPCHK(launch_links_form<T>(g, U[b].ptr, ctx->W[b].p, true, s));
