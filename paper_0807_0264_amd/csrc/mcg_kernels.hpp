@@ -580,8 +580,11 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
     if (threadIdx.x == 0) st->kfold = st->k;
     return;
   }
-  if ((what == BK_RESET || what == BK_CHECK) && st->done) return;
+  // the state is read once, alongside the partial sums (the two loads do not wait for each
+  // other); a finished field's block leaves after the sum, together (the exit is block-uniform)
+  const FixState sv = *st;
   const double s = sum_partials<256, 32>(d.part, d.npart);
+  if ((what == BK_RESET || what == BK_CHECK) && sv.done) return;
   if (threadIdx.x != 0) return;
   const double R = s / (9.0 * (double)(4 * d.g.V));
   switch (what) {
@@ -591,7 +594,7 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
     st->dR = 0.0;
     st->k = 0;
     st->kfold = 0;
-    st->done = st->max_k <= 0 ? 1 : 0;
+    st->done = sv.max_k <= 0 ? 1 : 0;
     st->status = 1;
     if (d.traj) d.traj[0] = R;
     break;
@@ -599,15 +602,16 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
     st->R_prev = R;
     break;
   case BK_CHECK: {
-    const double dR = R - st->R_prev;
-    st->k += 1;
+    const double dR = R - sv.R_prev;
+    const int k = sv.k + 1;
+    st->k = k;
     st->dR = dR;
     st->R_last = R;
-    if (d.traj) d.traj[st->k] = R;
-    if (dR < st->tol && (st->start_sweep + st->k) % st->stop_every == 0) {
+    if (d.traj) d.traj[k] = R;
+    if (dR < sv.tol && (sv.start_sweep + k) % sv.stop_every == 0) {
       st->done = 1;
       st->status = 0;
-    } else if (st->k >= st->max_k) {
+    } else if (k >= sv.max_k) {
       st->done = 1;
       st->status = 1;
     } else {
