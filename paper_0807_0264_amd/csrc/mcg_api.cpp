@@ -626,7 +626,7 @@ mcg_status mcg_destroy(mcg_ctx *ctx) {
                     &ctx->line_a, &ctx->line_b, &ctx->wl_part, &ctx->wl_res};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
-  for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj})
+  for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj, &ctx->gring})
     for (DevBuf &b : *v)
       if (b.p) (void)hipFree(b.p);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);

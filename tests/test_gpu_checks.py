@@ -95,3 +95,4 @@ def test_scratch_limit(S, g):
         assert st == A.MCG_WNOTCONV and r.sweeps == 1
     finally:
         assert lib.mcg_destroy(ctx) == A.MCG_OK
+
