@@ -96,3 +96,36 @@ def test_scratch_limit(S, g):
     finally:
         assert lib.mcg_destroy(ctx) == A.MCG_OK
 
+
+def test_destroy_returns_device_memory(S, g):
+    """A context that ran an FP32 fix (working field, transform, transform
+    ring, partial sums) and the batched tuner gives all of its device memory
+    back when destroyed."""
+    import ctypes as C
+
+    import torch
+    from paper_0807_0264_amd import _abi as A
+    from paper_0807_0264_amd import api
+    lib = A.load()
+    L = (16, 16, 16, 32)
+    U = api.to_links(S.haar_links_gpu(L, 12), 1)
+    G = api.gauge_identity(L)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    ctx = C.c_void_p()
+    assert lib.mcg_create(C.byref(ctx), torch.cuda.current_device()) == A.MCG_OK
+    try:
+        f, gg = U.abi(), G.abi()
+        best, ms = C.c_int32(), (C.c_double * A.MCG_NUM_VARIANTS)()
+        assert lib.mcg_autotune_batch(ctx, 1, C.byref(f), C.byref(best), ms, api._stream()) == A.MCG_OK
+        o = api._opts(-1.0, 30, 1.7, 50, 0, 50, None)
+        r = A.FixResult()
+        assert lib.mcg_fix(ctx, C.byref(f), C.byref(gg), C.byref(o), C.byref(r), api._stream()) == A.MCG_WNOTCONV
+        torch.cuda.synchronize()
+        held = free0 - torch.cuda.mem_get_info()[0]
+        # at 16^3x32: W two-row 25 MB, G two-row 13 MB, ring of 25 sweeps 157 MB, identity 19 MB
+        assert held > 150 << 20, held
+    finally:
+        assert lib.mcg_destroy(ctx) == A.MCG_OK
+    torch.cuda.synchronize()
+    assert free0 - torch.cuda.mem_get_info()[0] < 8 << 20
