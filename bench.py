@@ -480,6 +480,15 @@ def main():
     value = total / elapsed
 
     roof = roofline(api, torch, fields[0][1])
+    # the same kernel inside the batch: the tuner's median over three rounds of 8 launches, each one
+    # half-sweep over all four fields, HIP events (no stop flags, no folds)
+    su_batch = sum(api.volume(L) for L, _, _ in fields) // 2
+    bps = roof["bytes_per_site_update"]
+    gbps = su_batch * bps / (ms[best] * 1e-3) / 1e9
+    roof["in_batch"] = dict(ms_per_launch=round(ms[best], 4), site_updates_per_launch=su_batch,
+                            bytes_per_launch=su_batch * bps, GBps=round(gbps, 1),
+                            frac=round(gbps / HBM_PEAK_GBS, 4),
+                            note="one half-sweep over the four fields of the step (autotuner timing)")
     roof["copy_ceiling_GBps"] = copy_ceiling(torch)
     log(f"roofline: {roof}")
     gribov = None if args.no_gribov else gribov_copies(api, synth, torch, fields[2][1])
