@@ -480,7 +480,7 @@ def main():
     value = total / elapsed
 
     roof = roofline(api, torch, fields[0][1])
-    # the same kernel inside the batch: the tuner's median over three rounds of 8 launches, each one
+    # the same kernel inside the batch: the tuner's median over three passes of 8 launches, each one
     # half-sweep over all four fields, HIP events (no stop flags, no folds)
     su_batch = sum(api.volume(L) for L, _, _ in fields) // 2
     bps = roof["bytes_per_site_update"]

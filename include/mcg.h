@@ -214,7 +214,7 @@ mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge 
 /* The half-sweep kernel has MCG_NUM_VARIANTS variants: variant v uses blocks
  * of {64, 128, 256}[v % 3] threads and targets 1 + v / 3 waves per SIMD.
  * mcg_autotune times every variant on a scratch copy of U (G = 1; U is not
- * modified) in the context's storage form, in three interleaved rounds of 8
+ * modified) in the context's storage form, in three interleaved passes of 8
  * half-sweeps each, keeps the variant with the smallest median for U's
  * precision and that form, and returns it (best_variant,
  * ms_per_halfsweep[MCG_NUM_VARIANTS] nullable, host: the medians).  The variant fixes the

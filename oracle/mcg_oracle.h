@@ -18,7 +18,7 @@
  * All extents must be even (>= 2) so that every link joins an even and an
  * odd site (checkerboard).
  *
- * Readings where the paper is silent (each is listed in the design doc):
+ * Readings where the paper is silent:
  *   - gauge transform  U^G_mu(x) = G(x) U_mu(x) G(x+mu)^dagger
  *   - MCG local update: minorise-maximise step over the SU(2) subgroups
  *     (0,1),(1,2),(0,2) with binomial over-relaxation omega

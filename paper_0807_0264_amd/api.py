@@ -387,7 +387,7 @@ def smear_mcg_backward(U, rho, eps, n, Gstar, ckpt_every=5):
 
 def autotune(U):
     """Time every half-sweep variant on a copy of U; keep and return the fastest
-    (median of three interleaved rounds)."""
+    (median of three interleaved passes)."""
     ctx = context(U.data.device.index)
     f = U.abi()
     best = C.c_int32()
@@ -399,7 +399,7 @@ def autotune(U):
 def autotune_batch(Us):
     """Time every half-sweep variant on copies of the fields Us (one
     precision), each launch covering the whole batch as fix_batch runs it;
-    keep and return the fastest (median of three interleaved rounds)."""
+    keep and return the fastest (median of three interleaved passes)."""
     ctx = context(Us[0].data.device.index)
     B = len(Us)
     F = (A.Field * B)(*[U.abi() for U in Us])

@@ -981,13 +981,13 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // Three rounds over the variants, interleaved so that a slow moment of the device does not
-  // count against one variant only; each variant is judged by the median of its three rounds.
+  // Three passes over the variants, interleaved so that a slow moment of the device does not
+  // count against one variant only; each variant is ranked by the median of its three timings.
   // Every launch covers the whole batch, as the fix's half-sweeps do.
-  constexpr int ROUNDS = 3;
-  double per[ROUNDS][NUM_VARIANTS] = {};
+  constexpr int PASSES = 3;
+  double per[PASSES][NUM_VARIANTS] = {};
   mcg_status rc = MCG_OK;
-  for (int round = 0; round < ROUNDS && rc == MCG_OK; round++)
+  for (int pass = 0; pass < PASSES && rc == MCG_OK; pass++)
     for (int v = 0; v < NUM_VARIANTS && rc == MCG_OK; v++) {
       int total = 0;
       for (int b = 0; b < B; b++) {
@@ -1021,7 +1021,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
         rc = fail(ctx, MCG_EHIP, "autotune variant %d: %s", v, hipGetErrorString(e));
         break;
       }
-      per[round][v] = (double)t / reps;
+      per[pass][v] = (double)t / reps;
     }
   double tbest = 1e300;
   int vbest = ctx->variant[prec][c12];
