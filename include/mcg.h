@@ -289,7 +289,10 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * block), that of mcg_sweeps 25.  Results are bit-identical to 0.  Costs
  * 48 * C * L0*L1*L2*L3 bytes of context scratch per field for a ring of C
  * sweeps (2C slots of 48 bytes per site of one parity; 1200 bytes per site at
- * C = 25); FP64 fixes always update G in place. */
+ * C = 25); FP64 fixes always update G in place.  The ring is reserved last
+ * and is optional: when it does not fit in device memory or under
+ * MCG_OPT_SCRATCH_LIMIT_MIB, the call updates G in place instead (the same
+ * results) and does not fail. */
 #define MCG_OPT_DEFER_G 9
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,

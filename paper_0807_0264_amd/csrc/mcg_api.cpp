@@ -168,6 +168,19 @@ size_t gauge_form_bytes(const mcg_dims &d, bool c12) {
 // the transform ring of an FP32 fix holding C sweeps: 2C slots of Vh two-row FP32 matrices
 size_t gring_bytes(const Geom &g, int C) { return (size_t)2 * C * 6 * g.Vh * sizeof(V2<float>); }
 
+// Reserve the rings of fields 0..B-1.  The ring is optional: when it does not fit (device memory or
+// the context's scratch limit), the call updates G in place instead, with the same results, and the
+// context's last error is left as it was.
+bool reserve_rings(mcg_ctx *ctx, int B, const mcg_field *U, int C) {
+  const std::string err = ctx->err;
+  for (int b = 0; b < B; b++)
+    if (ensure(ctx, ctx->gring[b], gring_bytes(geom_of(U[b].d), C)) != MCG_OK) {
+      ctx->err = err;
+      return false;
+    }
+  return true;
+}
+
 // ------------------------------------------------------------ fixing driver
 // Largest |(M M^dag - 1)_ij| over U's links (and G's matrices when G is given), NaN as inf; host
 // results, synchronises the stream.
@@ -344,7 +357,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     ctx->traj.resize(B);
     ctx->gring.resize(B);
   }
-  const bool ring = prec == MCG_F32 && ctx->defer_g;
+  bool ring = prec == MCG_F32 && ctx->defer_g;
   mcg_status st;
   if ((st = ensure(ctx, ctx->states, sizeof(FixState) * B))) return st;
   if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>) * B))) return st;
@@ -358,7 +371,6 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12)))) return st;
     if (c12 && (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, true)))) return st;
     if ((st = ensure(ctx, ctx->fpart[b], sizeof(double) * nb * (bs / 64)))) return st;
-    if (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(g, gring_sweeps(re))))) return st;
     const bool want_traj = opts[b].traj != nullptr;
     if (want_traj && (st = ensure(ctx, ctx->traj[b], sizeof(double) * (opts[b].max_sweeps + 1)))) return st;
     LatDesc<T> d;
@@ -372,7 +384,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     d.part = (double *)ctx->fpart[b].p;
     d.npart = nb * (bs / 64);
     d.traj = want_traj ? (double *)ctx->traj[b].p : nullptr;
-    d.gring = ring ? (V2<T> *)ctx->gring[b].p : nullptr;
+    d.gring = nullptr;
     hD[b] = d;
     FixState f;
     memset(&f, 0, sizeof f);
@@ -383,6 +395,9 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     hS[b] = f;
     total += nb;
   }
+  // the ring last, after everything the fix cannot do without
+  if (ring) ring = reserve_rings(ctx, B, U, gring_sweeps(re));
+  for (int b = 0; b < B && ring; b++) hD[b].gring = (V2<T> *)ctx->gring[b].p;
   FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
   run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
   run.hits = ctx->hits;
@@ -853,10 +868,10 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   if (c12 && ((st = ensure(ctx, ctx->w12, work_field_bytes(W->d, W->prec, true))) ||
               (st = ensure(ctx, ctx->g12, gauge_form_bytes(W->d, true)))))
     return st;
-  const bool ring = parity < 0 && W->prec == MCG_F32 && ctx->defer_g;
+  bool ring = parity < 0 && W->prec == MCG_F32 && ctx->defer_g;
   if (ring) {
     if (ctx->gring.empty()) ctx->gring.resize(1);
-    if ((st = ensure(ctx, ctx->gring[0], gring_bytes(g, GRING_SWEEPS)))) return st;
+    ring = reserve_rings(ctx, 1, W, GRING_SWEEPS);
   }
   // the pinned staging area may still feed an earlier copy on this stream
   HIPCHK(hipStreamSynchronize(s));
@@ -942,7 +957,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   const bool c12 = ctx->c12;
   const int prec = U[0].prec;
   // time the half-sweep the fixes run: with the transform ring (FP32) g goes to ring slots 0 and 1
-  const bool ring = prec == MCG_F32 && ctx->defer_g;
+  bool ring = prec == MCG_F32 && ctx->defer_g;
   mcg_status st;
   if ((int)ctx->W.size() < B) {
     ctx->W.resize(B);
@@ -959,12 +974,12 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   size_t gfull = 0;
   for (int b = 0; b < B; b++) {
     if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12))) ||
-        (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, c12))) ||
-        (ring && (st = ensure(ctx, ctx->gring[b], gring_bytes(geom_of(U[b].d), 1)))))
+        (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, c12))))
       return st;
     gfull = std::max(gfull, mcg_gauge_bytes(U[b].d));
   }
   if (c12 && (st = ensure(ctx, ctx->grad_a, gfull))) return st;
+  if (ring) ring = reserve_rings(ctx, B, U, 1);
   for (int b = 0; b < B; b++) {
     const Geom g = geom_of(U[b].d);
     if (c12) {

@@ -97,6 +97,46 @@ def test_scratch_limit(S, g):
         assert lib.mcg_destroy(ctx) == A.MCG_OK
 
 
+def test_ring_falls_back_under_the_scratch_limit(S, g):
+    """A scratch limit that admits an FP32 fix but not its transform ring: the
+    fix runs with G updated in place, gives the bits of a fix with the ring
+    switched off, and leaves no error behind."""
+    import ctypes as C
+
+    import torch
+    from paper_0807_0264_amd import _abi as A
+    from paper_0807_0264_amd import api
+    lib = A.load()
+    L = (16, 16, 16, 32)
+    U = api.to_links(S.haar_links_gpu(L, 13), 1)
+
+    def run(ctx):
+        G = api.gauge_identity(L)
+        traj = np.zeros(41)
+        o = api._opts(-1.0, 40, 1.7, 50, 0, 50, traj)
+        r = A.FixResult()
+        f, gg = U.abi(), G.abi()
+        st = lib.mcg_fix(ctx, C.byref(f), C.byref(gg), C.byref(o), C.byref(r), api._stream())
+        torch.cuda.synchronize()
+        return st, g.host_gauge(G), traj
+
+    ctxs = [C.c_void_p(), C.c_void_p()]
+    for c in ctxs:
+        assert lib.mcg_create(C.byref(c), torch.cuda.current_device()) == A.MCG_OK
+    try:
+        # W (25 MB) and G (13 MB) in the two-row form fit in 64 MiB, the ring of 25 sweeps (157 MB) does not
+        assert lib.mcg_set_option(ctxs[0], A.MCG_OPT_SCRATCH_LIMIT_MIB, 64) == A.MCG_OK
+        st, Ga, ta = run(ctxs[0])
+        assert st == A.MCG_WNOTCONV and lib.mcg_last_error(ctxs[0]) == b""
+        assert lib.mcg_set_option(ctxs[1], A.MCG_OPT_DEFER_G, 0) == A.MCG_OK
+        st, Gb, tb = run(ctxs[1])
+        assert st == A.MCG_WNOTCONV
+        assert np.array_equal(Ga, Gb) and np.array_equal(ta, tb)
+    finally:
+        for c in ctxs:
+            assert lib.mcg_destroy(c) == A.MCG_OK
+
+
 def test_destroy_returns_device_memory(S, g):
     """A context that ran an FP32 fix (working field, transform, transform
     ring, partial sums) and the batched tuner gives all of its device memory
