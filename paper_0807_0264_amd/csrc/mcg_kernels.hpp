@@ -113,6 +113,15 @@ __device__ __forceinline__ void sphere_max(double Q[4][4], const double h[4], do
 #pragma unroll
     for (int c = 0; c < 4; c++) V[r][c] = r == c ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 10; sweep++) {
+    // converged: the off-diagonal part is below rounding against the diagonal
+    double off = 0.0, dia = 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+      dia += Q[p][p] * Q[p][p];
+#pragma unroll
+      for (int q = p + 1; q < 4; q++) off += Q[p][q] * Q[p][q];
+    }
+    if (!(off > 1e-34 * dia)) break;
 #pragma unroll
     for (int p = 0; p < 4; p++)
 #pragma unroll
@@ -179,6 +188,7 @@ __device__ __forceinline__ void sphere_max(double Q[4][4], const double h[4], do
     double lo = qtop, hi = qtop + sqrt(hn);
     for (int it = 0; it < 80; it++) {
       const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;  // the bracket cannot be split further
       double phi = 0.0;
 #pragma unroll
       for (int m = 0; m < 4; m++) phi += (hp[m] / (mid - q[m])) * (hp[m] / (mid - q[m]));
