@@ -132,3 +132,24 @@ def test_fix_properties_full(O, big):
     W = api.apply_gauge(U, G)
     assert abs(api.plaquette(W) - api.plaquette(U)) < 1e-5
     assert abs(api.functional(W) - info["R"]) < 1e-6
+
+
+def test_order_and_ring_are_bitwise_at_full_size(big):
+    """At the benchmark's size and launch variant, 60 sweeps (a re-unitarisation, two ring folds
+    and the final one) with the alternating tile order and the transform ring give the bits of
+    forward-order sweeps that update G in place."""
+    import torch
+    api, U, host, best = big
+    runs = []
+    try:
+        for on in (True, False):
+            api.set_sweep_order(on)
+            api.set_defer_g(on)
+            G, info = api.fix(U, None, tol=-1.0, max_sweeps=60, want_traj=True)
+            torch.cuda.synchronize()
+            runs.append((G.data.cpu().numpy(), info["traj"]))
+            del G
+    finally:
+        api.set_sweep_order(True)
+        api.set_defer_g(True)
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
