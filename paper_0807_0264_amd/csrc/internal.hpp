@@ -83,24 +83,35 @@ hipError_t launch_unitarity(const Geom &g, const void *U, int nmu, double *part,
 
 // k_loops.hip -- vortex-only / vortex-removed fields and Wilson loops.
 // A spatial path for the line kernel: n unit steps +-(axis+1), displacement d.
-struct SPathArg {
+constexpr int MAX_PATH = 32;
+// a spatial step sequence: steps +-(axis + 1), axis < 3
+struct SPath {
   int n;
-  int d[3];
-  int s[32];
+  int d[3];  // displacement of the whole path
+  signed char s[MAX_PATH];
 };
+// One image of a spatial path in a batched Wilson-loop launch: its steps, its weight in the
+// average, and its two line fields (line k is built into a if k is odd, else into b, from the other).
+template <typename T> struct LoopImage {
+  SPath path;
+  double weight;
+  V2<T> *a, *b;
+};
+// images per batched Wilson-loop launch (each holds two line fields)
+constexpr int LOOP_IMAGES_PER_LAUNCH = 16;
 template <typename T>
 hipError_t launch_vortex_field(const Geom &g, const void *U, const double *G, const int8_t *Z, int mode, void *out,
                                hipStream_t s);
 int line_blocks(const Geom &g);
-// out(x) = in(x) * path product from x + off (in null: 1); line fields hold 9 V complex of T
+// for every image (device array of nimg <= LOOP_IMAGES_PER_LAUNCH): line k = line k - 1 times the
+// path's links from x + (k - 1) d (line 0: 1); a line field holds 9 V complex of T
 template <typename T>
-hipError_t launch_line(const Geom &g, const void *U, const void *in, const SPathArg &path, const int off[3],
-                       void *out, hipStream_t s);
-// res[t] += weight * sum_x Re tr(loop with spatial line S, displacement D, time extent t + 1),
-// t < tmax; part holds tmax * line_blocks(g) doubles
+hipError_t launch_lines(const Geom &g, const void *U, const LoopImage<T> *imgs, int nimg, int k, hipStream_t s);
+// res[t] += sum over the images of weight * sum_x Re tr(loop with spatial line k of the image,
+// displacement k d, time extent t + 1), t < tmax; part holds nimg * tmax * line_blocks(g) doubles
 template <typename T>
-hipError_t launch_wloop(const Geom &g, const void *U, const void *S, const int D[3], int tmax, double *part,
-                        double weight, double *res, hipStream_t s);
+hipError_t launch_wloops(const Geom &g, const void *U, const LoopImage<T> *imgs, int nimg, int k, int tmax,
+                         double *part, double *res, hipStream_t s);
 hipError_t launch_zero(double *p, int n, hipStream_t s);
 
 // k_backward.hip -- adjoint of one smearing step and the loss seed.

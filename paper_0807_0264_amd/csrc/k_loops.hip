@@ -20,23 +20,17 @@ hipError_t launch_vortex_field(const Geom &g, const void *U, const double *G, co
 int line_blocks(const Geom &g) { return 2 * ((g.Vh + 255) / 256); }
 
 template <typename T>
-hipError_t launch_line(const Geom &g, const void *U, const void *in, const SPathArg &path, const int off[3],
-                       void *out, hipStream_t s) {
-  SPath p;
-  p.n = path.n;
-  for (int k = 0; k < 3; k++) p.d[k] = path.d[k];
-  for (int k = 0; k < MAX_PATH; k++) p.s[k] = k < path.n ? (signed char)path.s[k] : 0;
-  k_line<T><<<line_blocks(g), 256, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)in, p, off[0], off[1], off[2],
-                                           (V2<T> *)out);
+hipError_t launch_lines(const Geom &g, const void *U, const LoopImage<T> *imgs, int nimg, int k, hipStream_t s) {
+  k_line<T><<<dim3(line_blocks(g), nimg), 256, 0, s>>>(g, (const V2<T> *)U, imgs, k);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_wloop(const Geom &g, const void *U, const void *S, const int D[3], int tmax, double *part,
-                        double weight, double *res, hipStream_t s) {
+hipError_t launch_wloops(const Geom &g, const void *U, const LoopImage<T> *imgs, int nimg, int k, int tmax,
+                         double *part, double *res, hipStream_t s) {
   const int nb = line_blocks(g);
-  k_wloop<T, 256><<<nb, 256, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)S, D[0], D[1], D[2], tmax, part);
-  k_wloop_final<<<tmax, 256, 0, s>>>(part, nb, weight, res);
+  k_wloop<T, 256><<<dim3(nb, nimg), 256, 0, s>>>(g, (const V2<T> *)U, imgs, k, tmax, part);
+  k_wloop_final<T><<<tmax, 256, 0, s>>>(part, nb, nimg, tmax, imgs, res);
   return hipGetLastError();
 }
 
@@ -48,10 +42,9 @@ hipError_t launch_zero(double *p, int n, hipStream_t s) {
 #define MCG_LOOPS_INST(T)                                                                                  \
   template hipError_t launch_vortex_field<T>(const Geom &, const void *, const double *, const int8_t *, int, \
                                              void *, hipStream_t);                                         \
-  template hipError_t launch_line<T>(const Geom &, const void *, const void *, const SPathArg &, const int *, \
-                                     void *, hipStream_t);                                                 \
-  template hipError_t launch_wloop<T>(const Geom &, const void *, const void *, const int *, int, double *,  \
-                                      double, double *, hipStream_t);
+  template hipError_t launch_lines<T>(const Geom &, const void *, const LoopImage<T> *, int, int, hipStream_t); \
+  template hipError_t launch_wloops<T>(const Geom &, const void *, const LoopImage<T> *, int, int, int, double *, \
+                                       double *, hipStream_t);
 MCG_LOOPS_INST(float)
 MCG_LOOPS_INST(double)
 

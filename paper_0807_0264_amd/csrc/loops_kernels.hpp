@@ -70,57 +70,57 @@ __global__ __launch_bounds__(256) void k_vortex_field(Geom g, const V2<T> *U, co
   }
 }
 
-constexpr int MAX_PATH = 32;
-// a spatial step sequence: steps +-(axis + 1), axis < 3
-struct SPath {
-  int n;
-  int d[3];  // displacement of the whole path
-  signed char s[MAX_PATH];
-};
-
-// out(x) = in(x) * (product of the links along `path` starting at x + off), in = null meaning 1.
-// Line fields use the link layout with a single direction.  Grid: 2 * ceil(Vh / 256) blocks,
-// the first half even sites, the second half odd sites.
+// For image blockIdx.y: line k of the image, out(x) = in(x) * (the path's links starting at
+// x + (k - 1) d), in = line k - 1 (none for k = 1).  Line fields use the link layout with a single
+// direction.  Grid: (2 * ceil(Vh / 256), images), the first half of x even sites, the second odd.
 template <typename T>
-__global__ __launch_bounds__(256) void k_line(Geom g, const V2<T> *__restrict__ U, const V2<T> *in, SPath path,
-                                              int o0, int o1, int o2, V2<T> *out) {
+__global__ __launch_bounds__(256) void k_line(Geom g, const V2<T> *__restrict__ U,
+                                              const LoopImage<T> *__restrict__ imgs, int k) {
+  const LoopImage<T> &im = imgs[blockIdx.y];
   const int nbp = gridDim.x >> 1;
   const int par = blockIdx.x >= nbp;
   const int h = (blockIdx.x - par * nbp) * 256 + threadIdx.x;
   if (h >= g.Vh) return;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
+  const V2<T> *in = k == 1 ? nullptr : ((k & 1) ? im.b : im.a);
+  V2<T> *out = (k & 1) ? im.a : im.b;
   int c[4];
   coords_of(g, par, h, c);
   M3<T> M = in ? Links<T>{const_cast<V2<T> *>(in), g.Vh}.load(0, par, h) : m_ident<T>();
   int y[4];
-  shifted(g, c, o0, o1, o2, 0, y);
-  for (int q = 0; q < path.n; q++) {
-    const int st = path.s[q];
+  shifted(g, c, (k - 1) * im.path.d[0], (k - 1) * im.path.d[1], (k - 1) * im.path.d[2], 0, y);
+  for (int q = 0; q < im.path.n; q++) {
+    const int st = im.path.s[q];
     const int a = (st > 0 ? st : -st) - 1;
     if (st > 0) {
       M = mul(M, L.at(g, y, a));
       int e[4];
       moved(g, y, a, +1, e);
 #pragma unroll
-      for (int k = 0; k < 4; k++) y[k] = e[k];
+      for (int q2 = 0; q2 < 4; q2++) y[q2] = e[q2];
     } else {
       int e[4];
       moved(g, y, a, -1, e);
 #pragma unroll
-      for (int k = 0; k < 4; k++) y[k] = e[k];
+      for (int q2 = 0; q2 < 4; q2++) y[q2] = e[q2];
       M = mul_nd(M, L.at(g, y, a));
     }
   }
   Links<T>{out, g.Vh}.store(0, par, h, M);
 }
 
-// For every site x: the loops with spatial side S(x) (a line field from x to x + D) and time
-// extents T = 1..tmax,  Re tr[ S(x) B_T(x+D) S(x+T)^dag A_T(x)^dag ],  A_T(y) = U_3(y) ... U_3(y+(T-1)),
-// summed per block into part[(T-1) * gridDim.x + blockIdx.x].  Each lane carries P = S(x) B_T(x+D)
-// and A_T(x), one product each per T, and forms Q = A_T(x) S(x+T): Re tr(P Q^dag).
+// For image blockIdx.y and every site x: the loops with spatial side S(x) (its line k, from x to
+// x + D, D = k d) and time extents T = 1..tmax, Re tr[ S(x) B_T(x+D) S(x+T)^dag A_T(x)^dag ],
+// A_T(y) = U_3(y) ... U_3(y+(T-1)), summed per block into
+// part[(image * tmax + T - 1) * gridDim.x + blockIdx.x].  Each lane carries P = S(x) B_T(x+D) and
+// A_T(x), one product each per T, and forms Q = A_T(x) S(x+T): Re tr(P Q^dag).
 template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ U, const V2<T> *__restrict__ S,
-                                              int D0, int D1, int D2, int tmax, double *__restrict__ part) {
+__global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ U,
+                                              const LoopImage<T> *__restrict__ imgs, int k, int tmax,
+                                              double *__restrict__ part) {
+  const LoopImage<T> &im = imgs[blockIdx.y];
+  const V2<T> *S = (k & 1) ? im.a : im.b;
+  const int D0 = k * im.path.d[0], D1 = k * im.path.d[1], D2 = k * im.path.d[2];
   const int nbp = gridDim.x >> 1;
   const int par = blockIdx.x >= nbp;
   const int h = (blockIdx.x - par * nbp) * BS + threadIdx.x;
@@ -135,6 +135,7 @@ __global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ 
     P = Sf.load(0, par, h);
     A = m_ident<T>();
   }
+  double *pt = part + (size_t)blockIdx.y * tmax * gridDim.x;
   for (int t = 1; t <= tmax; t++) {
     double val = 0.0;
     if (live) {
@@ -146,19 +147,25 @@ __global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ 
       shifted(g, c, 0, 0, 0, t, e);
       const M3<T> Q = mul(A, Sf.load(0, parity_of(e), half_index(g, e)));
 #pragma unroll
-      for (int k = 0; k < 9; k++)
-        val += (double)P.e[k].re * (double)Q.e[k].re + (double)P.e[k].im * (double)Q.e[k].im;
+      for (int q = 0; q < 9; q++)
+        val += (double)P.e[q].re * (double)Q.e[q].re + (double)P.e[q].im * (double)Q.e[q].im;
     }
     const double s = block_sum<BS>(val);
-    if (threadIdx.x == 0) part[(size_t)(t - 1) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) pt[(size_t)(t - 1) * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// res[t] += weight * sum_b part[t * nb + b] (fixed order); one block per t
-__global__ __launch_bounds__(256) void k_wloop_final(const double *__restrict__ part, int nb, double weight,
-                                                     double *res) {
-  const double s = sum_partials<256>(part + (size_t)blockIdx.x * nb, nb);
-  if (threadIdx.x == 0) res[blockIdx.x] += weight * s;
+// res[t] += sum over the images, in order, of weight * sum_b part[(image * tmax + t) * nb + b]
+// (each block sum in a fixed order); one block per t
+template <typename T>
+__global__ __launch_bounds__(256) void k_wloop_final(const double *__restrict__ part, int nb, int nimg, int tmax,
+                                                     const LoopImage<T> *__restrict__ imgs, double *res) {
+  double r = threadIdx.x == 0 ? res[blockIdx.x] : 0.0;
+  for (int i = 0; i < nimg; i++) {
+    const double s = sum_partials<256>(part + ((size_t)i * tmax + blockIdx.x) * nb, nb);
+    if (threadIdx.x == 0) r += imgs[i].weight * s;
+  }
+  if (threadIdx.x == 0) res[blockIdx.x] = r;
 }
 
 __global__ __launch_bounds__(256) void k_zero(double *p, int n) {

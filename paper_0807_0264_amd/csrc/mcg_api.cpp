@@ -33,7 +33,7 @@ struct mcg_ctx {
   std::string err;
   hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
   DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part, w12, g12;
-  DevBuf line_a, line_b, wl_part, wl_res;  // Wilson loops: line fields, partial sums, results
+  DevBuf line_a, line_b, wl_part, wl_res, wl_img;  // Wilson loops: line fields, partial sums, results, images
   std::vector<DevBuf> W, G12, fpart, traj, gring;
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
@@ -638,7 +638,7 @@ mcg_status mcg_destroy(mcg_ctx *ctx) {
   (void)hipDeviceSynchronize();
   DevBuf *bufs[] = {&ctx->part, &ctx->scalars, &ctx->counts, &ctx->states, &ctx->desc, &ctx->tmpfield,
                     &ctx->grad_a, &ctx->grad_b, &ctx->gC, &ctx->ckpt, &ctx->bw_part, &ctx->w12, &ctx->g12,
-                    &ctx->line_a, &ctx->line_b, &ctx->wl_part, &ctx->wl_res};
+                    &ctx->line_a, &ctx->line_b, &ctx->wl_part, &ctx->wl_res, &ctx->wl_img};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj, &ctx->gring})
@@ -1369,37 +1369,49 @@ mcg_status wilson_impl(mcg_ctx *ctx, const mcg_field *U, int nvec, const int32_t
   const Geom g = geom_of(U->d);
   const size_t line_bytes = (size_t)g.V * 9 * 2 * sizeof(T);
   const int nres = nvec * rmax * tmax;
+  // images per launch: up to LOOP_IMAGES_PER_LAUNCH, as many as keep their line fields within 4 GiB
+  const int ni = (int)std::max<size_t>(
+      1, std::min<size_t>(LOOP_IMAGES_PER_LAUNCH, ((size_t)4 << 30) / (2 * line_bytes)));
   mcg_status st;
-  if ((st = ensure(ctx, ctx->line_a, line_bytes)) || (st = ensure(ctx, ctx->line_b, line_bytes)) ||
-      (st = ensure(ctx, ctx->wl_part, sizeof(double) * (size_t)tmax * line_blocks(g))) ||
-      (st = ensure(ctx, ctx->wl_res, sizeof(double) * (size_t)nres)))
+  if ((st = ensure(ctx, ctx->line_a, line_bytes * ni)) || (st = ensure(ctx, ctx->line_b, line_bytes * ni)) ||
+      (st = ensure(ctx, ctx->wl_part, sizeof(double) * (size_t)ni * tmax * line_blocks(g))) ||
+      (st = ensure(ctx, ctx->wl_res, sizeof(double) * (size_t)nres)) ||
+      (st = ensure(ctx, ctx->wl_img, sizeof(LoopImage<T>) * ni)) ||
+      (st = ensure_pinned(ctx, sizeof(LoopImage<T>) * ni)))
     return st;
   double *res = (double *)ctx->wl_res.p;
+  LoopImage<T> *hI = (LoopImage<T> *)ctx->h_pinned;
+  const LoopImage<T> *dI = (const LoopImage<T> *)ctx->wl_img.p;
   HIPCHK(launch_zero(res, nres, s));
   for (int i = 0; i < nvec; i++) {
     const int v[3] = {vec[3 * i], vec[3 * i + 1], vec[3 * i + 2]};
     const auto imgs = path_images(staircase_steps(v));
     int nimg = 0;
     for (const auto &e : imgs) nimg += e.second;
-    for (const auto &e : imgs) {
-      SPathArg p;
-      p.n = (int)e.first.size();
-      p.d[0] = p.d[1] = p.d[2] = 0;
-      for (int q = 0; q < p.n; q++) {
-        p.s[q] = e.first[q];
-        p.d[std::abs(p.s[q]) - 1] += p.s[q] > 0 ? 1 : -1;
+    for (size_t c0 = 0; c0 < imgs.size(); c0 += ni) {
+      const int n = (int)std::min<size_t>(ni, imgs.size() - c0);
+      // the staging area and the descriptor table may still feed the previous chunk's launches
+      HIPCHK(hipStreamSynchronize(s));
+      for (int j = 0; j < n; j++) {
+        const auto &e = imgs[c0 + j];
+        LoopImage<T> d;
+        memset(&d, 0, sizeof d);
+        d.path.n = (int)e.first.size();
+        for (int q = 0; q < d.path.n; q++) {
+          d.path.s[q] = (signed char)e.first[q];
+          d.path.d[std::abs(e.first[q]) - 1] += e.first[q] > 0 ? 1 : -1;
+        }
+        // Re tr / 3, averaged over sites and images
+        d.weight = (double)e.second / (3.0 * (double)nimg * (double)g.V);
+        d.a = (V2<T> *)((char *)ctx->line_a.p + (size_t)j * line_bytes);
+        d.b = (V2<T> *)((char *)ctx->line_b.p + (size_t)j * line_bytes);
+        hI[j] = d;
       }
-      // Re tr / 3, averaged over sites and images
-      const double weight = (double)e.second / (3.0 * (double)nimg * (double)g.V);
-      const void *prev = nullptr;
+      HIPCHK(hipMemcpyAsync(ctx->wl_img.p, hI, sizeof(LoopImage<T>) * n, hipMemcpyHostToDevice, s));
       for (int k = 1; k <= rmax; k++) {
-        void *cur = (k & 1) ? ctx->line_a.p : ctx->line_b.p;
-        const int off[3] = {(k - 1) * p.d[0], (k - 1) * p.d[1], (k - 1) * p.d[2]};
-        const int D[3] = {k * p.d[0], k * p.d[1], k * p.d[2]};
-        HIPCHK(launch_line<T>(g, U->ptr, prev, p, off, cur, s));
-        HIPCHK(launch_wloop<T>(g, U->ptr, cur, D, tmax, (double *)ctx->wl_part.p, weight,
-                               res + (size_t)(i * rmax + k - 1) * tmax, s));
-        prev = cur;
+        HIPCHK(launch_lines<T>(g, U->ptr, dI, n, k, s));
+        HIPCHK(launch_wloops<T>(g, U->ptr, dI, n, k, tmax, (double *)ctx->wl_part.p,
+                                res + (size_t)(i * rmax + k - 1) * tmax, s));
       }
     }
   }
