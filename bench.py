@@ -39,6 +39,11 @@ HBM_PEAK_GBS = 8000.0
 # full matrices 72 B and 144 B.
 BYTES_PER_SITE_UPDATE = {(True, True): 8 * 48 * 2 + 48, (True, False): 8 * 48 * 2 + 2 * 96,
                          (False, True): 8 * 72 * 2 + 48, (False, False): 8 * 72 * 2 + 2 * 144}
+# paired sweeps (two-row form with the ring): the even half-sweep reads the 8 links and writes g
+# (8 * 48 + 48 B per site), the odd one reads the 8 links and the even g of its neighbours (each
+# g needed once: 48 B per site), writes the 8 links and its own g (8 * 48 * 2 + 48 + 48); per
+# site-update the mean of the two
+BYTES_PER_SITE_UPDATE_PAIRED = (8 * 48 + 48 + 8 * 48 * 2 + 48 + 48) // 2
 # the fold kernel's bytes per site-update it folds, with 25 sweeps per fold (raw sweeps, and
 # fixes re-unitarising every 50): g read once (48 B) + G(x) read and written once per 25
 FOLD_BYTES_PER_SITE_UPDATE = {True: 48 + 2 * 96 / 25, False: 48 + 2 * 144 / 25}
@@ -304,7 +309,8 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
     import statistics
     ms = statistics.median(api.sweeps_timed(W, G, nsweeps) / (2 * nsweeps) for _ in range(runs))
     two_row, defer = api.get_two_row(), api.get_defer_g()
-    bps = BYTES_PER_SITE_UPDATE[(two_row, defer)]
+    paired = two_row and defer and api.get_paired()
+    bps = BYTES_PER_SITE_UPDATE_PAIRED if paired else BYTES_PER_SITE_UPDATE[(two_row, defer)]
     site_updates = api.volume(U.L) // 2
     achieved = site_updates * bps / (ms * 1e-3) / 1e9
     traffic = None
@@ -325,7 +331,8 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
                 kernel="k_halfsweep<float,%s> (one parity of 32^3x64, %s, %s)" % (
                     "two-row" if two_row else "full",
                     "alternating tile order" if api.get_sweep_order() else "forward tile order",
-                    "g to the transform ring" if defer else "G updated in place"),
+                    ("paired sweeps, g to the transform ring" if paired else "g to the transform ring")
+                    if defer else "G updated in place"),
                 ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps,
                 sweep_loop=dict(ms_per_half_sweep=round(loop_ms, 4), bytes_per_site_update=loop_bps,
                                 GBps=round(site_updates * loop_bps / (loop_ms * 1e-3) / 1e9, 1),
@@ -511,6 +518,8 @@ def main():
                             else "forward",
                             transform="per-half-sweep g in a ring, folded into G every 25 sweeps"
                             if api.get_defer_g() else "G updated in every half-sweep",
+                            sweeps="paired: the even half-sweep leaves the links to the odd one"
+                            if api.get_defer_g() and api.get_paired() else "plain half-sweeps",
                             per_field=[dict(L=x["L"], sweeps_smeared=x["sweeps_smeared"], sweeps=x["sweeps"],
                                             R_smeared=round(x["R_smeared"], 7), R=round(x["R"], 7),
                                             vortex_fraction=round(x["vortex_fraction"], 5))

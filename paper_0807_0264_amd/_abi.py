@@ -21,6 +21,7 @@ MCG_OPT_SCRATCH_LIMIT_MIB = 6
 MCG_OPT_EXACT = 7
 MCG_OPT_ORDER = 8
 MCG_OPT_DEFER_G = 9
+MCG_OPT_PAIRED = 10
 MCG_VORTEX_ONLY, MCG_VORTEX_REMOVED = 0, 1
 
 

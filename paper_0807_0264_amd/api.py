@@ -449,6 +449,21 @@ def get_defer_g(device=None):
     return bool(v.value)
 
 
+def set_paired(on, device=None):
+    """With the transform ring (FP32, two-row form): the first half-sweep of
+    each sweep only records its transform, the second applies it to the links
+    as it loads them (bit-identical, each link written once per sweep)."""
+    ctx = context(device)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_PAIRED, 1 if on else 0), ctx)
+
+
+def get_paired(device=None):
+    ctx = context(device)
+    v = C.c_int32()
+    _check(A.load().mcg_get_option(ctx, A.MCG_OPT_PAIRED, C.byref(v)), ctx)
+    return bool(v.value)
+
+
 def get_sweep_order(device=None):
     ctx = context(device)
     v = C.c_int32()

@@ -399,28 +399,51 @@ template <typename T> struct Links12 {
   }
 };
 
-// ------------------------------------------- transform updates in fixed FP64
-// G <- g G written with explicit fused multiply-adds in a fixed order, and the
-// two-row reconstruction likewise: the compiler contracts plain products into
-// FMAs as it sees fit in each kernel, so two kernels doing "the same" product
-// can differ in the last bit; these give the same bits wherever they are inlined.
-__device__ __forceinline__ cx<double> dot3_fma(cx<double> a0, cx<double> b0, cx<double> a1, cx<double> b1,
-                                               cx<double> a2, cx<double> b2) {
-  double re = a0.re * b0.re, im = a0.re * b0.im;
-  re = fma(-a0.im, b0.im, re);
-  im = fma(a0.im, b0.re, im);
-  re = fma(a1.re, b1.re, re);
-  re = fma(-a1.im, b1.im, re);
-  im = fma(a1.re, b1.im, im);
-  im = fma(a1.im, b1.re, im);
-  re = fma(a2.re, b2.re, re);
-  re = fma(-a2.im, b2.im, re);
-  im = fma(a2.re, b2.im, im);
-  im = fma(a2.im, b2.re, im);
-  return cx<double>{re, im};
+// ----------------------------------------- products in a fixed FMA order
+// G <- g G, the link updates of the half-sweep and the two-row reconstruction,
+// written with explicit fused multiply-adds in a fixed order: the compiler
+// contracts plain products into FMAs as it sees fit in each kernel, so two
+// kernels doing "the same" product can differ in the last bit; these give the
+// same bits wherever they are inlined.
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return fmaf(a, b, c);
+  else return fma(a, b, c);
 }
-__device__ __forceinline__ M3<double> mul_fixed(const M3<double> &a, const M3<double> &b) {
-  M3<double> c;
+// a0 b0 + a1 b1 + a2 b2
+template <typename T>
+__device__ __forceinline__ cx<T> dot3_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = a0.re * b0.re, im = a0.re * b0.im;
+  re = fma_t(-a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(-a1.im, b1.im, re);
+  im = fma_t(a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(-a2.im, b2.im, re);
+  im = fma_t(a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+// a0 conj(b0) + a1 conj(b1) + a2 conj(b2)
+template <typename T>
+__device__ __forceinline__ cx<T> dot3c_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = a0.re * b0.re, im = -(a0.re * b0.im);
+  re = fma_t(a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(a1.im, b1.im, re);
+  im = fma_t(-a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(a2.im, b2.im, re);
+  im = fma_t(-a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+// a b
+template <typename T> __device__ __forceinline__ M3<T> mul_fixed(const M3<T> &a, const M3<T> &b) {
+  M3<T> c;
 #pragma unroll
   for (int r = 0; r < 3; r++)
 #pragma unroll
@@ -428,18 +451,48 @@ __device__ __forceinline__ M3<double> mul_fixed(const M3<double> &a, const M3<do
       c.e[3 * r + q] = dot3_fma(a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
   return c;
 }
-// conj(x y - z w), the product terms fused in a fixed order
-__device__ __forceinline__ cx<double> cross_fma(cx<double> x, cx<double> y, cx<double> z, cx<double> w) {
-  double re = x.re * y.re, im = x.re * y.im;
-  re = fma(-x.im, y.im, re);
-  im = fma(x.im, y.re, im);
-  re = fma(-z.re, w.re, re);
-  re = fma(z.im, w.im, re);
-  im = fma(-z.re, w.im, im);
-  im = fma(-z.im, w.re, im);
-  return cx<double>{re, -im};
+// a b^dagger
+template <typename T> __device__ __forceinline__ M3<T> mul_nd_fixed(const M3<T> &a, const M3<T> &b) {
+  M3<T> c;
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3c_fma(a.e[3 * r], b.e[3 * q], a.e[3 * r + 1], b.e[3 * q + 1], a.e[3 * r + 2], b.e[3 * q + 2]);
+  return c;
 }
-__device__ __forceinline__ void third_row_fixed(M3<double> &m) {
+// rows 0 and 1 of a b and of a b^dagger (row 2 zero); the first needs all of b, the second only
+// rows 0 and 1 of a
+template <typename T> __device__ __forceinline__ M3<T> mul_fixed_rows(const M3<T> &a, const M3<T> &b) {
+  M3<T> c = m_zero<T>();
+#pragma unroll
+  for (int r = 0; r < 2; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3_fma(a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
+  return c;
+}
+template <typename T> __device__ __forceinline__ M3<T> mul_nd_fixed_rows(const M3<T> &a, const M3<T> &b) {
+  M3<T> c = m_zero<T>();
+#pragma unroll
+  for (int r = 0; r < 2; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3c_fma(a.e[3 * r], b.e[3 * q], a.e[3 * r + 1], b.e[3 * q + 1], a.e[3 * r + 2], b.e[3 * q + 2]);
+  return c;
+}
+// conj(x y - z w), the product terms fused in a fixed order
+template <typename T> __device__ __forceinline__ cx<T> cross_fma(cx<T> x, cx<T> y, cx<T> z, cx<T> w) {
+  T re = x.re * y.re, im = x.re * y.im;
+  re = fma_t(-x.im, y.im, re);
+  im = fma_t(x.im, y.re, im);
+  re = fma_t(-z.re, w.re, re);
+  re = fma_t(z.im, w.im, re);
+  im = fma_t(-z.re, w.im, im);
+  im = fma_t(-z.im, w.re, im);
+  return cx<T>{re, -im};
+}
+template <typename T> __device__ __forceinline__ void third_row_fixed(M3<T> &m) {
   m.e[6] = cross_fma(m.e[1], m.e[5], m.e[2], m.e[4]);
   m.e[7] = cross_fma(m.e[2], m.e[3], m.e[0], m.e[5]);
   m.e[8] = cross_fma(m.e[0], m.e[4], m.e[1], m.e[3]);

@@ -18,10 +18,14 @@ template <typename T>
 // slab < 0: the whole of every field (blocks = total); slab >= 0: that slab's chunks (blocks = their total)
 // hits > 1 (re-linearisation hits) or exact (exact subgroup maximisation) requires variant 2
 // (256-thread blocks); rev: tiles in reverse grid order (same results, other visiting order);
-// gslot >= 0: g goes to that slot of each field's transform ring instead of into G (k_fold)
+// gslot >= 0: g goes to that slot of each field's transform ring instead of into G (k_fold);
+// paired sweeps (two-row form with the ring): keep = 1 leaves the links as they are (the first
+// half-sweep of a sweep), pend >= 0 names the ring slot whose g the links still wait for (the
+// second half-sweep applies it as it loads them); the first half runs 3 + variant / 3 waves per SIMD
+// (it has no link products), the second 1 + variant / 3 like a plain half-sweep
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0,
-                            int rev = 0, int gslot = -1);
+                            int rev = 0, int gslot = -1, int pend = -1, int keep = 0);
 // fold the ring's transforms into G (nfix: the count for fields without a FixState)
 template <typename T>
 hipError_t launch_fold(int bs, bool c12, const void *D, int B, int blocks, int nfix, hipStream_t s);

@@ -27,13 +27,36 @@ namespace mcg {
 template <typename T>
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s, int slab, int hits, int exact, int rev,
-                            int gslot) {
+                            int gslot, int pend, int keep) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
+  // the paired form needs the two-row working field and a ring slot for the first half's g
+  if ((pend >= 0 || keep) && !c12) return hipErrorInvalidValue;
+  if (keep && (gslot < 0 || pend >= 0 || withR || sizeof(T) != 4)) return hipErrorInvalidValue;
   if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
 #define MCG_HM(WR, C, E) \
-  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, hits)
+  k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend, hits)
+    if constexpr (sizeof(T) == 4) {
+      if (keep) {  // the first half of a paired sweep: the links stay, g goes to the ring
+#define MCG_HK(E) \
+  k_halfsweep<T, 256, false, 1, true, true, E, KEEP><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend, hits)
+        if (exact) MCG_HK(true); else MCG_HK(false);
+#undef MCG_HK
+        return hipGetLastError();
+      }
+      if (pend >= 0) {  // the second half: the pending g applied as the links are loaded
+#define MCG_HP(WR, E) \
+  k_halfsweep<T, 256, WR, 1, true, true, E, PEND><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend, hits)
+        if (exact) {
+          if (withR) MCG_HP(true, true); else MCG_HP(false, true);
+        } else {
+          if (withR) MCG_HP(true, false); else MCG_HP(false, false);
+        }
+#undef MCG_HP
+        return hipGetLastError();
+      }
+    }
     if (exact) {
       if (c12) {
         if (withR) MCG_HM(true, true, true); else MCG_HM(false, true, true);
@@ -51,7 +74,28 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
     return hipGetLastError();
   }
 #define MCG_HS(WR, OCC, C)                                                                         \
-  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot)))
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, C><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend)))
+#define MCG_HK(OCC) \
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, false, OCC, true, false, false, KEEP><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend)))
+#define MCG_HP(WR, OCC) \
+  MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, true, false, false, PEND><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend)))
+  if constexpr (sizeof(T) == 4) {
+    if (keep) {
+      // no link products: three waves per SIMD without spills (variants 0-2), four with a few (3-5)
+      if (variant / 3 == 0) { MCG_HK(3); } else { MCG_HK(4); }
+      return hipGetLastError();
+    }
+    if (pend >= 0) {
+      if (variant / 3 == 0) {
+        if (withR) { MCG_HP(true, 1); } else { MCG_HP(false, 1); }
+      } else {
+        if (withR) { MCG_HP(true, 2); } else { MCG_HP(false, 2); }
+      }
+      return hipGetLastError();
+    }
+  }
+#undef MCG_HK
+#undef MCG_HP
   if (c12) {
     if (variant / 3 == 0) {
       if (withR) { MCG_HS(true, 1, true); } else { MCG_HS(false, 1, true); }
@@ -133,7 +177,7 @@ hipError_t launch_gauge_form(const Geom &g, const double *src, double *dst, bool
 
 #define MCG_INST(T)                                                                                  \
   template hipError_t launch_halfsweep<T>(int, bool, const void *, int, int, int, double, bool, bool,  \
-                                          hipStream_t, int, int, int, int, int);                     \
+                                          hipStream_t, int, int, int, int, int, int, int);           \
   template hipError_t launch_fold<T>(int, bool, const void *, int, int, int, hipStream_t);            \
   template hipError_t launch_rederive<T>(int, bool, const void *, int, int, bool, hipStream_t);       \
   template hipError_t launch_reunit<T>(int, bool, const void *, int, int, bool, hipStream_t);         \

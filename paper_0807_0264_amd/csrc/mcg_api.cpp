@@ -43,6 +43,7 @@ struct mcg_ctx {
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
   int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order (MCG_OPT_ORDER)
   bool defer_g = true;  // FP32 fixes keep each half-sweep's g in a ring, folded into G later (MCG_OPT_DEFER_G)
+  bool paired = true;   // with the ring, the first half-sweep of a sweep leaves the links to the second
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
   size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
   size_t scratch_used = 0;
@@ -268,12 +269,18 @@ template <typename T> struct FixRun {
   int C = 0;
   int since_fold = 0;
   bool stateful = true;  // fields carry a FixState (the fold count comes from it)
+  // Paired sweeps (two-row form with the ring): the even half-sweep only records g in its slot,
+  // the odd one applies it to the links it loads.
+  bool paired = false;
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
+    const int slot = C ? 2 * since_fold + par : -1;
+    const bool pr = paired && C && c12;
     if (blocks > 0)
       HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact,
-                                 order && par == 1, C ? 2 * since_fold + par : -1));
+                                 order && par == 1, slot, pr && par == 1 ? slot - 1 : -1,
+                                 pr && par == 0 ? 1 : 0));
     return MCG_OK;
   }
   // Launched whatever since_fold says on the host: a field's own count decides what is folded,
@@ -404,6 +411,7 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
   run.C = ring ? gring_sweeps(re) : 0;
+  run.paired = ctx->paired;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -889,6 +897,7 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
   run.C = ring ? GRING_SWEEPS : 0;
+  run.paired = ctx->paired;
   run.stateful = false;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
@@ -980,6 +989,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   }
   if (c12 && (st = ensure(ctx, ctx->grad_a, gfull))) return st;
   if (ring) ring = reserve_rings(ctx, B, U, 1);
+  const bool pr = ring && c12 && ctx->paired;  // paired sweeps, as the fixes run them
   for (int b = 0; b < B; b++) {
     const Geom g = geom_of(U[b].d);
     if (c12) {
@@ -1022,12 +1032,14 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       for (int k = 0; k < 4 && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                ctx->order && (k & 1), ring ? (k & 1) : -1);
+                                ctx->order && (k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       const int reps = 8;
       for (int k = 0; k < reps && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                ctx->order && (k & 1), ring ? (k & 1) : -1);
+                                ctx->order && (k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float t = 0.f;
@@ -1121,6 +1133,11 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     ctx->defer_g = value != 0;
     return MCG_OK;
   }
+  if (option == MCG_OPT_PAIRED) {
+    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_PAIRED takes 0 or 1");
+    ctx->paired = value != 0;
+    return MCG_OK;
+  }
   if (option == MCG_OPT_CHECK) {
     if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_CHECK takes 0 or 1");
     ctx->check = value != 0;
@@ -1173,6 +1190,10 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
   }
   if (option == MCG_OPT_DEFER_G) {
     *value = ctx->defer_g ? 1 : 0;
+    return MCG_OK;
+  }
+  if (option == MCG_OPT_PAIRED) {
+    *value = ctx->paired ? 1 : 0;
     return MCG_OK;
   }
   if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {

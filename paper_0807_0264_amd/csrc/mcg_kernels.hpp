@@ -284,6 +284,18 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
     for (int j = 0; j < 3; j++) X.e[3 * i + j] = X.e[3 * i + j] + t * conj(b.e[3 * j + i]);
 }
 
+// rows 0 and 1 of the g at half index h in one ring slot (row 2 zero)
+template <typename T> __device__ __forceinline__ M3<T> ring_g(const V2<T> *slot, int Vh, int h) {
+  M3<T> m = m_zero<T>();
+  const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    const V2<T> v = ld_plane(slot + (size_t)k * Vh, o);
+    m.e[k] = cx<T>{v.x, v.y};
+  }
+  return m;
+}
+
 // ----------------------------------------------------------- half-sweep
 // Every site x of parity `par` gathers its eight links (forward W_mu(x),
 // backward W_mu(x-mu)^dag), builds X, g, and writes g W_mu(x),
@@ -298,10 +310,21 @@ template <typename T> __device__ __forceinline__ void axpy_dag(cx<T> t, const M3
 // linearises sum_k |tr(g M_k)|^2 at the current g, X_g = sum_k conj(tr(g M_k)) M_k, and runs
 // the subgroup steps on g X_g, continuing g.  EXACT: each subgroup step instead maximises
 // sum_k |tr(s g M_k)|^2 over its subgroup exactly (then over-relaxes), `hits` rounds of three.
-template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false>
+// Paired sweeps (C12 with the transform ring): the first half-sweep of a sweep leaves the links
+// alone (keep) and only records its g in ring slot gslot; the second (pend = that slot) applies
+// the pending g of each neighbour to the links it loads, exactly as the first half-sweep would
+// have stored them, before its own update.  Every link then joins one site of each parity, so it
+// is read twice and written once per sweep instead of read and written twice, and the result is
+// that of two plain half-sweeps bit for bit: the link products in both modes are fixed FMA
+// sequences with row 2 of g rebuilt from rows 0 and 1, the form the ring keeps.
+// MODE: PLAIN, KEEP (first half of a paired sweep) or PEND (second half; pend names the slot).
+enum { PLAIN = 0, KEEP = 1, PEND = 2 };
+template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false,
+          int MODE = PLAIN>
 __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restrict__ D, int B, int par,
                                                        T omega, int gated, int slab, int rev, int gslot,
-                                                       int hits = 1) {
+                                                       int pend, int hits = 1) {
+  constexpr bool keep = MODE == KEEP;
   using WS = typename FixStore<T, C12>::W;
   using GS = typename FixStore<T, C12>::G;
   int lb;
@@ -317,11 +340,13 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
     coords_of(d.g, par, h, c);
     const unsigned of = W.off(par, h);
     unsigned ob[4];
+    int hb[4];
 #pragma unroll
     for (int mu = 0; mu < 4; mu++) {
       int e[4];
       moved(d.g, c, mu, -1, e);
-      ob[mu] = W.off(1 - par, half_index(d.g, e));
+      hb[mu] = half_index(d.g, e);
+      ob[mu] = W.off(1 - par, hb[mu]);
     }
     M3<T> F[4], Bk[4];
 #pragma unroll
@@ -333,6 +358,35 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
     for (int mu = 0; mu < 4; mu++) {
       if constexpr (C12) Bk[mu] = W.load_rows(mu, ob[mu]);
       else Bk[mu] = W.load_off(mu, ob[mu]);
+    }
+    if constexpr (C12 && MODE == PEND) {
+      {
+        // the other parity's g of this sweep, pending on the links: W_mu(x) g'(x+mu)^dag and
+        // g'(x-mu) W_mu(x-mu), rows 0 and 1 as that half-sweep would have stored them
+        // all eight loads issued before the first product, so they are in flight together
+        const V2<T> *ring = d.gring + (size_t)pend * 6 * d.g.Vh;
+        M3<T> gf[4], gb[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+          int e[4];
+          moved(d.g, c, mu, +1, e);
+          gf[mu] = ring_g<T>(ring, d.g.Vh, half_index(d.g, e));
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) gb[mu] = ring_g<T>(ring, d.g.Vh, hb[mu]);
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+          third_row_fixed(gf[mu]);
+          F[mu] = mul_nd_fixed_rows(F[mu], gf[mu]);
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+          third_row_fixed(gb[mu]);
+          M3<T> b = Bk[mu];
+          third_row_fixed(b);
+          Bk[mu] = mul_fixed_rows(gb[mu], b);
+        }
+      }
     }
 
     M3<T> X = m_zero<T>();
@@ -383,38 +437,57 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       }
     }
 
+    if constexpr (C12) {
+      // g as the ring keeps it (rows 0 and 1, row 2 rebuilt), applied in a fixed FMA order
+      M3<T> gr = g;
+      third_row_fixed(gr);
+      if (!keep) {
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) {
-      M3<T> f = F[mu];
-      if constexpr (C12) {
-        opaque_rows(f);
-        third_row(f);
-      }
-      const M3<T> fn = mul(g, f);
-      W.store_off(mu, of, fn);
-      if (WR) r += tr2(fn);
-    }
+        for (int mu = 0; mu < 4; mu++) {
+          M3<T> f = F[mu];
+          opaque_rows(f);
+          third_row_fixed(f);
+          const M3<T> fn = mul_fixed(gr, f);
+          W.store_off(mu, of, fn);
+          if (WR) r += tr2(fn);
+        }
 #pragma unroll
-    for (int mu = 0; mu < 4; mu++) {
-      M3<T> bk = Bk[mu];
-      if constexpr (C12) {
-        opaque_rows(bk);
-        third_row(bk);
+        for (int mu = 0; mu < 4; mu++) {
+          M3<T> bk = Bk[mu];
+          opaque_rows(bk);
+          third_row_fixed(bk);
+          const M3<T> bn = mul_nd_fixed(bk, gr);
+          W.store_off(mu, ob[mu], bn);
+          if (WR) r += tr2(bn);
+        }
       }
-      const M3<T> bn = mul_nd(bk, g);
-      W.store_off(mu, ob[mu], bn);
-      if (WR) r += tr2(bn);
+    } else {
+#pragma unroll
+      for (int mu = 0; mu < 4; mu++) {
+        const M3<T> fn = mul(g, F[mu]);
+        W.store_off(mu, of, fn);
+        if (WR) r += tr2(fn);
+      }
+#pragma unroll
+      for (int mu = 0; mu < 4; mu++) {
+        const M3<T> bn = mul_nd(Bk[mu], g);
+        W.store_off(mu, ob[mu], bn);
+        if (WR) r += tr2(bn);
+      }
     }
-    if (gslot >= 0) {
+    if (keep || gslot >= 0) {
       // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold); streaming
-      // stores leave the last-level cache to the links that the next half-sweep reads
+      // stores leave the last-level cache to the links that the next half-sweep reads, except
+      // where that half-sweep reads this g (keep)
       const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
 #pragma unroll
       for (int k = 0; k < 6; k++) {
         V2<T> v;
         v.x = g.e[k].re;
         v.y = g.e[k].im;
-        st_plane_stream(d.gring + ((size_t)gslot * 6 + k) * d.g.Vh, o, v);
+        V2<T> *plane = d.gring + ((size_t)gslot * 6 + k) * d.g.Vh;
+        if (keep) st_plane(plane, o, v);
+        else st_plane_stream(plane, o, v);
       }
     } else {
       M3<double> gd = m_cvt<double>(g);

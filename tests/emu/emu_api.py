@@ -291,6 +291,10 @@ def set_defer_g(on):
     check(lib().mcg_set_option(ctx(), 9, 1 if on else 0))
 
 
+def set_paired(on):
+    check(lib().mcg_set_option(ctx(), 10, 1 if on else 0))
+
+
 def set_check(on):
     check(lib().mcg_set_option(ctx(), 5, 1 if on else 0))
 

@@ -190,9 +190,10 @@ def scenario_slabs(prec):
     G1 = S.haar_gauge(L1, S.sub_seed(2062))
     E.set_variant(prec, 0)  # 64-thread blocks: 8 blocks per half-sweep of L1, split into 2 or 3 slabs
     ref = None
-    for n, order in ((1, 0), (2, 0), (3, 0), (1, 1), (3, 1)):
+    for n, order, paired in ((1, 0, 1), (2, 0, 1), (3, 0, 1), (1, 1, 1), (3, 1, 1), (3, 1, 0), (1, 0, 0)):
         E.set_slabs(n)
         E.set_sweep_order(order)
+        E.set_paired(paired)
         G, info = E.fix(E.links(U1, prec), E.gauge(G1), tol=-1.0, max_sweeps=5, reunit_every=2, check_every=2)
         infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], [E.gauge_identity(L2), E.gauge(G1)],
                             [-1.0, -1.0], [4, 5], reunit_every=2, check_every=2)
@@ -204,8 +205,9 @@ def scenario_slabs(prec):
             check(np.array_equal(got[1], got[3]), "batch equals single")
         else:
             check(all(np.array_equal(a, b) for a, b in zip(got, ref)),
-                  f"slabs {n} order {order} differ from whole forward half-sweeps")
+                  f"slabs {n} order {order} paired {paired} differ from whole forward half-sweeps")
     E.set_slabs(1)
+    E.set_paired(True)
     # 20 blocks of 64 sites per half-sweep: residue classes mod 8 of three and two blocks
     L3 = (4, 4, 4, 40)
     U3 = rounded(field(L3, 2063), prec)
@@ -249,9 +251,10 @@ def scenario_variants(prec):
 
 def scenario_defer():
     """FP32: the transform ring (each half-sweep's g folded into G later) gives
-    the bits of updating G in every half-sweep: a batch where one field stops
-    early, blocks replayed from a captured graph, more sweeps than the ring
-    holds, both storage forms, raw sweeps."""
+    the bits of updating G in every half-sweep, and paired sweeps (the first
+    half-sweep leaves the links to the second) the bits of plain ones: a batch
+    where one field stops early, blocks replayed from a captured graph, more
+    sweeps than the ring holds, both storage forms, raw sweeps."""
     prec = 1
     L1, L2 = (4, 4, 4, 16), (4, 2, 2, 4)
     U1, U2 = rounded(field(L1, 2090), prec), rounded(field(L2, 2091), prec)
@@ -259,8 +262,9 @@ def scenario_defer():
     for two_row in (True, False):
         E.set_two_row(two_row)
         got = []
-        for defer in (True, False):
+        for defer, paired in ((True, True), (True, False), (False, True)):
             E.set_defer_g(defer)
+            E.set_paired(paired)
             Gs = [E.gauge_identity(L2), E.gauge(G1)]
             infos = E.fix_batch([E.links(U2, prec), E.links(U1, prec)], Gs, [1e-5, -1.0], [70, 70],
                                 reunit_every=30, check_every=5)
@@ -271,8 +275,11 @@ def scenario_defer():
             got.append([infos[0]["traj"], infos[1]["traj"], infos[0]["sweeps"], info["traj"], E.host_gauge(G),
                         E.host_links(W), E.host_gauge(Gd)] + [E.host_gauge(x) for x in Gs])
         check(got[0][2] < 70, f"the small field stops early ({got[0][2]} sweeps)")
-        for k, (a, b) in enumerate(zip(*got)):
-            check(np.array_equal(a, b), f"ring and in-place transform differ (item {k}, two_row={two_row})")
+        for m in (1, 2):
+            for k, (a, b) in enumerate(zip(got[0], got[m])):
+                check(np.array_equal(a, b), f"mode {m} differs from paired sweeps with the ring "
+                                            f"(item {k}, two_row={two_row})")
+    E.set_paired(True)
     E.set_defer_g(True)
     E.set_two_row(True)
 

@@ -136,15 +136,17 @@ def test_fix_properties_full(O, big):
 
 def test_order_and_ring_are_bitwise_at_full_size(big):
     """At the benchmark's size and launch variant, 60 sweeps (a re-unitarisation, two ring folds
-    and the final one) with the alternating tile order and the transform ring give the bits of
-    forward-order sweeps that update G in place."""
+    and the final one) with the alternating tile order, the transform ring and paired sweeps give
+    the bits of forward-order plain sweeps that update G in place, and of the ring without
+    paired sweeps."""
     import torch
     api, U, host, best = big
     runs = []
     try:
-        for on in (True, False):
-            api.set_sweep_order(on)
-            api.set_defer_g(on)
+        for order, defer, paired in ((True, True, True), (False, False, False), (True, True, False)):
+            api.set_sweep_order(order)
+            api.set_defer_g(defer)
+            api.set_paired(paired)
             G, info = api.fix(U, None, tol=-1.0, max_sweeps=60, want_traj=True)
             torch.cuda.synchronize()
             runs.append((G.data.cpu().numpy(), info["traj"]))
@@ -152,4 +154,6 @@ def test_order_and_ring_are_bitwise_at_full_size(big):
     finally:
         api.set_sweep_order(True)
         api.set_defer_g(True)
-    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+        api.set_paired(True)
+    for m in (1, 2):
+        assert np.array_equal(runs[0][0], runs[m][0]) and np.array_equal(runs[0][1], runs[m][1]), m

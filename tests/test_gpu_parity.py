@@ -361,10 +361,12 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
 @pytest.mark.parametrize("two_row", [True, False])
 def test_transform_ring_is_bitwise(S, g, api, two_row):
     """FP32: each half-sweep's g kept in the ring and folded into G later gives
-    the bits of updating G in every half-sweep: a batch where one field stops
-    early, blocks of 30 sweeps replayed from a captured graph (ring of 15:
-    a fold inside each block and one at its start), a standalone fix (ring
-    of 25, 37 sweeps) and raw sweeps."""
+    the bits of updating G in every half-sweep, and paired sweeps (the even
+    half-sweep leaves the links to the odd one, which applies the even g as it
+    loads them) the bits of plain ones: a batch where one field stops early,
+    blocks of 30 sweeps replayed from a captured graph (ring of 15: a fold
+    inside each block and one at its start), a standalone fix (ring of 25, 37
+    sweeps) and raw sweeps."""
     prec = 1
     L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
     U1 = g.rounded(field(S, L1, 1055), prec)
@@ -373,9 +375,10 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
     got = []
     try:
         api.set_two_row(two_row)
-        for defer in (True, False):
+        for defer, paired in ((True, True), (True, False), (False, True)):
             api.set_defer_g(defer)
-            assert api.get_defer_g() == defer
+            api.set_paired(paired)
+            assert api.get_defer_g() == defer and api.get_paired() == paired
             Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)],
                                       [api.gauge_identity(L2), g.gauge(G1)], tol=[1e-4, -1.0],
                                       max_sweeps=[130, 130], reunit_every=30, check_every=5, want_traj=True)
@@ -386,11 +389,13 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
             got.append([infos[0]["traj"], infos[1]["traj"], infos[0]["sweeps"], g.host_gauge(Gb[0]),
                         g.host_gauge(Gb[1]), info["traj"], g.host_gauge(G), g.host_links(W), g.host_gauge(Gd)])
     finally:
+        api.set_paired(True)
         api.set_defer_g(True)
         api.set_two_row(True)
     assert got[0][2] < 130
-    for k, (a, b) in enumerate(zip(*got)):
-        assert np.array_equal(a, b), k
+    for m in (1, 2):
+        for k, (a, b) in enumerate(zip(got[0], got[m])):
+            assert np.array_equal(a, b), (m, k)
 
 
 @pytest.mark.parametrize("prec", PRECS)
