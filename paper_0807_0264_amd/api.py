@@ -429,10 +429,12 @@ def set_slabs(n, device=None):
 
 
 def set_sweep_order(alternate, device=None):
-    """alternate=True: odd half-sweeps visit the lattice tiles in reverse
-    order, starting where the even half-sweep ended (bit-identical results)."""
+    """alternate=True (1): odd half-sweeps visit the lattice tiles in reverse
+    order, starting where the even half-sweep ended; 2: the same with a
+    contiguous range of tiles per XCD (bit-identical results)."""
     ctx = context(device)
-    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_ORDER, 1 if alternate else 0), ctx)
+    v = 2 if (not isinstance(alternate, bool) and alternate == 2) else (1 if alternate else 0)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_ORDER, v), ctx)
 
 
 def set_defer_g(on, device=None):
@@ -468,7 +470,7 @@ def get_sweep_order(device=None):
     ctx = context(device)
     v = C.c_int32()
     _check(A.load().mcg_get_option(ctx, A.MCG_OPT_ORDER, C.byref(v)), ctx)
-    return bool(v.value)
+    return v.value
 
 
 def unitarity(U=None, G=None):

@@ -41,7 +41,7 @@ struct mcg_ctx {
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
-  int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order (MCG_OPT_ORDER)
+  int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order; 2: and each XCD a contiguous range (MCG_OPT_ORDER)
   bool defer_g = true;  // FP32 fixes keep each half-sweep's g in a ring, folded into G later (MCG_OPT_DEFER_G)
   bool paired = true;   // with the ring, the first half-sweep of a sweep leaves the links to the second
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
@@ -250,6 +250,9 @@ template <typename T> int plan_slabs(LatDesc<T> *D, int B, int n, int bs, int gr
   return n;
 }
 
+// the tile-order argument of a half-sweep of parity par: bit 0 reverse, bit 1 contiguous XCD ranges
+static int tile_order(int order, int par) { return order == 0 ? 0 : (order == 2 ? 2 : 0) | (par == 1 ? 1 : 0); }
+
 template <typename T> struct FixRun {
   mcg_ctx *ctx;
   hipStream_t s;
@@ -279,7 +282,7 @@ template <typename T> struct FixRun {
     const bool pr = paired && C && c12;
     if (blocks > 0)
       HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact,
-                                 order && par == 1, slot, pr && par == 1 ? slot - 1 : -1,
+                                 tile_order(order, par), slot, pr && par == 1 ? slot - 1 : -1,
                                  pr && par == 0 ? 1 : 0));
     return MCG_OK;
   }
@@ -903,7 +906,7 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
   if (parity >= 0) {
     HIPCHK(launch_halfsweep<T>(variant, false, ctx->desc.p, 1, nb, parity, omega, false, false, s, -1, ctx->hits,
-                               ctx->exact ? 1 : 0, ctx->order && parity == 1));
+                               ctx->exact ? 1 : 0, tile_order(ctx->order, parity)));
     return MCG_OK;
   }
   if (c12) {
@@ -1032,13 +1035,13 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       for (int k = 0; k < 4 && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                ctx->order && (k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
                                 pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       const int reps = 8;
       for (int k = 0; k < reps && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                ctx->order && (k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
                                 pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1124,7 +1127,7 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     return MCG_OK;
   }
   if (option == MCG_OPT_ORDER) {
-    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_ORDER takes 0 or 1");
+    if (value < 0 || value > 2) return fail(ctx, MCG_EINVAL, "MCG_OPT_ORDER takes 0, 1 or 2");
     ctx->order = value;
     return MCG_OK;
   }

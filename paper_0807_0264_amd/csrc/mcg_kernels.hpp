@@ -24,12 +24,17 @@ __device__ __forceinline__ int find_field(const LatDesc<T> *__restrict__ D, int 
 // residue class mod 8: grid block x + 8j takes tile x + 8(c_x - 1 - j), c_x
 // the number of blocks of residue x; every tile stays on the XCD (and its
 // L2) that handles it in the forward order.
+// rev & 2: XCD x instead takes a contiguous range of c_x tiles (its j-th block the j-th tile of the
+// range, or with rev & 1 the j-th from its end), so the tiles a site's neighbours lie in, a few
+// tiles away along z, are mostly handled by the same XCD and meet in its L2.
 __device__ __forceinline__ int tile_of_block(int rev) {
   const int b = (int)blockIdx.x;
   if (!rev) return b;
-  const int n = (int)gridDim.x, x = b & 7;
-  const int cx = (n >> 3) + (x < (n & 7) ? 1 : 0);
-  return x + 8 * (cx - 1 - (b >> 3));
+  const int n = (int)gridDim.x, x = b & 7, j = b >> 3;
+  const int q = n >> 3, r = n & 7;
+  const int cx = q + (x < r ? 1 : 0);
+  if (rev & 2) return x * q + (x < r ? x : r) + ((rev & 1) ? cx - 1 - j : j);
+  return x + 8 * (cx - 1 - j);
 }
 
 template <typename T>

@@ -284,7 +284,7 @@ def set_update_variant(hits, stop_every, exact=False):
 
 
 def set_sweep_order(alternate):
-    check(lib().mcg_set_option(ctx(), 8, 1 if alternate else 0))
+    check(lib().mcg_set_option(ctx(), 8, int(alternate)))
 
 
 def set_defer_g(on):

@@ -190,7 +190,8 @@ def scenario_slabs(prec):
     G1 = S.haar_gauge(L1, S.sub_seed(2062))
     E.set_variant(prec, 0)  # 64-thread blocks: 8 blocks per half-sweep of L1, split into 2 or 3 slabs
     ref = None
-    for n, order, paired in ((1, 0, 1), (2, 0, 1), (3, 0, 1), (1, 1, 1), (3, 1, 1), (3, 1, 0), (1, 0, 0)):
+    for n, order, paired in ((1, 0, 1), (2, 0, 1), (3, 0, 1), (1, 1, 1), (3, 1, 1), (3, 1, 0), (1, 0, 0),
+                             (1, 2, 1), (3, 2, 1)):
         E.set_slabs(n)
         E.set_sweep_order(order)
         E.set_paired(paired)
@@ -212,11 +213,12 @@ def scenario_slabs(prec):
     L3 = (4, 4, 4, 40)
     U3 = rounded(field(L3, 2063), prec)
     got = []
-    for order in (0, 1):
+    for order in (0, 1, 2):
         E.set_sweep_order(order)
         G, info = E.fix(E.links(U3, prec), None, tol=-1.0, max_sweeps=4, reunit_every=2, check_every=2)
         got.append((E.host_gauge(G), info["traj"]))
-    check(all(np.array_equal(a, b) for a, b in zip(*got)), "reverse tile order differs on 20 blocks")
+    for m in (1, 2):
+        check(all(np.array_equal(a, b) for a, b in zip(got[0], got[m])), f"tile order {m} differs on 20 blocks")
     E.set_sweep_order(0)
     E.set_variant(prec, 2)
 

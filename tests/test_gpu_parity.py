@@ -326,15 +326,16 @@ def test_synth_gpu_is_bitwise_cpu(S, g):
 @pytest.mark.parametrize("prec", PRECS)
 def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
     """Half-sweeps run slab by slab (several slab counts, a batch mixing a
-    split and an unsplit field), and odd half-sweeps in reverse tile order,
-    give the bits of whole forward half-sweeps."""
+    split and an unsplit field), and odd half-sweeps in reverse tile order
+    (also with contiguous tile ranges per XCD), give the bits of whole
+    forward half-sweeps."""
     L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
     U1 = g.rounded(field(S, L1, 1050), prec)
     U2 = g.rounded(field(S, L2, 1051), prec)
     G1 = S.haar_gauge(L1, S.sub_seed(1052))
     ref = None
     try:
-        for n, order in ((1, False), (2, False), (5, False), (8, False), (1, True), (5, True)):
+        for n, order in ((1, False), (2, False), (5, False), (8, False), (1, True), (5, True), (1, 2), (5, 2)):
             api.set_slabs(n)
             api.set_sweep_order(order)
             assert api.get_sweep_order() == order
