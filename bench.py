@@ -330,7 +330,8 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel="k_halfsweep<float,%s> (one parity of 32^3x64, %s, %s)" % (
                     "two-row" if two_row else "full",
-                    "alternating tile order" if api.get_sweep_order() else "forward tile order",
+                    {0: "forward tile order", 1: "alternating tile order",
+                     2: "alternating tile order, XCD ranges per field"}[api.get_sweep_order()],
                     ("paired sweeps, g to the transform ring" if paired else "g to the transform ring")
                     if defer else "G updated in place"),
                 ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps,
@@ -514,8 +515,9 @@ def main():
                                      "batched MCG fix to dR<1e-7 (omega=1.7), carried-back batched "
                                      "re-fix, centre projection, vortex count",
                             links="fp32", gauge="fp64", reductions="fp64", half_sweep_variant=best,
-                            sweep_order="odd half-sweeps in reverse tile order" if api.get_sweep_order()
-                            else "forward",
+                            sweep_order={0: "forward", 1: "odd half-sweeps in reverse tile order",
+                                         2: "odd half-sweeps in reverse tile order; each XCD a "
+                                            "contiguous range of every field's tiles"}[api.get_sweep_order()],
                             transform="per-half-sweep g in a ring, folded into G every 25 sweeps"
                             if api.get_defer_g() else "G updated in every half-sweep",
                             sweeps="paired: the even half-sweep leaves the links to the odd one"

@@ -269,17 +269,18 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * with MCG_OPT_HITS, the three exact steps repeat `hits` times.  Runs with
  * 256-thread blocks. */
 #define MCG_OPT_EXACT 7
-/* MCG_OPT_ORDER (0/1/2, default 1): 1 makes every odd half-sweep visit the
+/* MCG_OPT_ORDER (0/1/2, default 2): 1 makes every odd half-sweep visit the
  * lattice tiles in reverse order, so it starts on the links the even
  * half-sweep wrote last (and the next even half-sweep on those the odd one
  * wrote last), which the last-level cache may still hold; the reversal keeps
  * each tile on the XCD that handles it in the forward order.  2: the same
- * alternation, with each XCD taking a contiguous range of tiles (so a site's
- * neighbours along z mostly lie on the same XCD, which helps the odd half of
- * a paired sweep on a single large lattice; slower on batches of several
- * fields).  0: every half-sweep in forward order.  Results are bit-identical
- * for all three: the sites of one parity are independent and the reduction
- * partials belong to tiles, not to the launch order. */
+ * alternation, and within each field the blocks that one XCD runs take a
+ * contiguous range of its tiles instead of every eighth tile, so a site's
+ * neighbours along z mostly lie on the same XCD (the odd half of a paired
+ * sweep reads the even g of all eight neighbours).  0: every half-sweep in
+ * forward order.  Results are bit-identical for all three: the sites of one
+ * parity are independent and the reduction partials belong to tiles, not to
+ * the launch order. */
 #define MCG_OPT_ORDER 8
 /* MCG_OPT_DEFER_G (0/1, default 1): with FP32 links, mcg_fix, mcg_fix_batch
  * and mcg_sweeps let each half-sweep write its per-site g (two rows, FP32)

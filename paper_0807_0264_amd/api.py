@@ -430,8 +430,9 @@ def set_slabs(n, device=None):
 
 def set_sweep_order(alternate, device=None):
     """alternate=True (1): odd half-sweeps visit the lattice tiles in reverse
-    order, starting where the even half-sweep ended; 2: the same with a
-    contiguous range of tiles per XCD (bit-identical results)."""
+    order, starting where the even half-sweep ended; 2 (the default): the
+    same, with each XCD taking a contiguous range of every field's tiles
+    (bit-identical results)."""
     ctx = context(device)
     v = 2 if (not isinstance(alternate, bool) and alternate == 2) else (1 if alternate else 0)
     _check(A.load().mcg_set_option(ctx, A.MCG_OPT_ORDER, v), ctx)

@@ -41,7 +41,7 @@ struct mcg_ctx {
   int nslab = 1;    // half-sweeps run slab by slab when > 1 (MCG_OPT_SLABS)
   int hits = 1;     // re-linearisation hits per site visit (MCG_OPT_HITS)
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
-  int order = 1;       // 1: odd half-sweeps visit the tiles in reverse order; 2: and each XCD a contiguous range (MCG_OPT_ORDER)
+  int order = 2;       // 1: odd half-sweeps visit the tiles in reverse order; 2: and each XCD a contiguous range (MCG_OPT_ORDER)
   bool defer_g = true;  // FP32 fixes keep each half-sweep's g in a ring, folded into G later (MCG_OPT_DEFER_G)
   bool paired = true;   // with the ring, the first half-sweep of a sweep leaves the links to the second
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)

@@ -24,17 +24,22 @@ __device__ __forceinline__ int find_field(const LatDesc<T> *__restrict__ D, int 
 // residue class mod 8: grid block x + 8j takes tile x + 8(c_x - 1 - j), c_x
 // the number of blocks of residue x; every tile stays on the XCD (and its
 // L2) that handles it in the forward order.
-// rev & 2: XCD x instead takes a contiguous range of c_x tiles (its j-th block the j-th tile of the
-// range, or with rev & 1 the j-th from its end), so the tiles a site's neighbours lie in, a few
-// tiles away along z, are mostly handled by the same XCD and meet in its L2.
 __device__ __forceinline__ int tile_of_block(int rev) {
   const int b = (int)blockIdx.x;
-  if (!rev) return b;
-  const int n = (int)gridDim.x, x = b & 7, j = b >> 3;
-  const int q = n >> 3, r = n & 7;
-  const int cx = q + (x < r ? 1 : 0);
-  if (rev & 2) return x * q + (x < r ? x : r) + ((rev & 1) ? cx - 1 - j : j);
-  return x + 8 * (cx - 1 - j);
+  if (!(rev & 1)) return b;
+  const int n = (int)gridDim.x, x = b & 7;
+  const int cx = (n >> 3) + (x < (n & 7) ? 1 : 0);
+  return x + 8 * (cx - 1 - (b >> 3));
+}
+
+// rev & 2: within each field's n blocks (or its chunk of a slab), the blocks i of one class
+// i mod 8 (one XCD) take a contiguous range of tiles, the j-th block of the class (i = class + 8j)
+// the j-th tile of the range, instead of every eighth tile; the tiles a site's neighbours lie in,
+// a few tiles away along z, are then mostly handled by the same XCD and meet in its L2.  Applied
+// after the reversal above, it keeps every tile on one XCD in both directions.
+__device__ __forceinline__ int xcd_range(int i, int n) {
+  const int x = i & 7, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
 }
 
 template <typename T>
@@ -45,13 +50,16 @@ __device__ __forceinline__ int block_of(const LatDesc<T> *__restrict__ D, int B,
     for (int i = 1; i < B; i++)
       if (vb >= D[i].blk0) b = i;
     local = vb - D[b].blk0;
+    if (rev & 2) local = xcd_range(local, D[b].nblk);
     return b;
   }
   int b = 0;
   for (int i = 1; i < B; i++)
     if (vb >= D[i].sblk0[slab]) b = i;
-  const int lo = D[b].nslab > 1 ? (slab * D[b].nblk) / D[b].nslab : 0;
-  local = lo + vb - D[b].sblk0[slab];
+  const int ns = D[b].nslab > 1 ? D[b].nslab : 1;
+  const int lo = ns > 1 ? (slab * D[b].nblk) / ns : 0, hi = ns > 1 ? ((slab + 1) * D[b].nblk) / ns : D[b].nblk;
+  const int i = vb - D[b].sblk0[slab];
+  local = lo + ((rev & 2) ? xcd_range(i, hi - lo) : i);
   return b;
 }
 

@@ -136,14 +136,14 @@ def test_fix_properties_full(O, big):
 
 def test_order_and_ring_are_bitwise_at_full_size(big):
     """At the benchmark's size and launch variant, 60 sweeps (a re-unitarisation, two ring folds
-    and the final one) with the alternating tile order, the transform ring and paired sweeps give
-    the bits of forward-order plain sweeps that update G in place, and of the ring without
-    paired sweeps."""
+    and the final one) with the default tile order (alternating, XCD ranges per field), the
+    transform ring and paired sweeps give the bits of forward-order plain sweeps that update G in
+    place, of the ring without paired sweeps, and of the alternating order without XCD ranges."""
     import torch
     api, U, host, best = big
     runs = []
     try:
-        for order, defer, paired in ((True, True, True), (False, False, False), (True, True, False)):
+        for order, defer, paired in ((2, True, True), (0, False, False), (2, True, False), (1, True, True)):
             api.set_sweep_order(order)
             api.set_defer_g(defer)
             api.set_paired(paired)
@@ -152,8 +152,8 @@ def test_order_and_ring_are_bitwise_at_full_size(big):
             runs.append((G.data.cpu().numpy(), info["traj"]))
             del G
     finally:
-        api.set_sweep_order(True)
+        api.set_sweep_order(2)
         api.set_defer_g(True)
         api.set_paired(True)
-    for m in (1, 2):
+    for m in (1, 2, 3):
         assert np.array_equal(runs[0][0], runs[m][0]) and np.array_equal(runs[0][1], runs[m][1]), m

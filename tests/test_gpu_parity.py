@@ -356,7 +356,7 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
                     assert np.array_equal(a, b), (n, order)
     finally:
         api.set_slabs(1)
-        api.set_sweep_order(False)
+        api.set_sweep_order(2)
 
 
 @pytest.mark.parametrize("two_row", [True, False])
