@@ -32,7 +32,8 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
   const int bs = variant_block(variant), g = gated ? 1 : 0;
   // the paired form needs the two-row working field and a ring slot for the first half's g
   if ((pend >= 0 || keep) && !c12) return hipErrorInvalidValue;
-  if (keep && (gslot < 0 || pend >= 0 || withR || sizeof(T) != 4)) return hipErrorInvalidValue;
+  if ((keep || pend >= 0) && sizeof(T) != 4) return hipErrorInvalidValue;  // the ring holds FP32 g
+  if (keep && (gslot < 0 || pend >= 0 || withR)) return hipErrorInvalidValue;
   if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
 #define MCG_HM(WR, C, E) \

@@ -338,6 +338,14 @@ def scenario_checks(prec):
         E.set_scratch_limit_mib(0)
     _, info = E.fix(E.links(U8, prec), None, tol=-1.0, max_sweeps=1)
     check(info["sweeps"] == 1, "usable after the limit")
+    # option values out of range: the tile order takes 0-2, paired sweeps and the ring 0 or 1
+    for opt, val in ((8, 3), (8, -1), (10, 2), (10, -1), (9, 2)):
+        check(E.lib().mcg_set_option(E.ctx(), opt, val) == -1, f"option {opt} = {val} rejected")
+    import ctypes
+    v = ctypes.c_int32()
+    for opt, want in ((8, 2), (9, 1), (10, 1)):
+        check(E.lib().mcg_get_option(E.ctx(), opt, ctypes.byref(v)) == 0 and v.value == want,
+              f"option {opt} keeps its default {want}")
 
 
 def main():

@@ -399,6 +399,32 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
             assert np.array_equal(a, b), (m, k)
 
 
+def test_paired_sweeps_with_hits_and_exact_steps(S, g, api):
+    """FP32 with the ring: paired sweeps give the bits of plain ones also for
+    re-linearisation hits and exact subgroup steps (their own 256-thread
+    instantiations of both halves), in a fix and in raw sweeps."""
+    prec = 1
+    L = (8, 8, 8, 16)
+    U = g.rounded(field(S, L, 1058), prec)
+    G0 = S.haar_gauge(L, S.sub_seed(1059))
+    try:
+        for hits, exact in ((3, False), (1, True), (2, True)):
+            api.set_update_variant(hits, 1, exact)
+            got = []
+            for paired in (True, False):
+                api.set_paired(paired)
+                G, info = api.fix(g.links(U, prec), g.gauge(G0), tol=-1.0, max_sweeps=30, reunit_every=20,
+                                  check_every=7, want_traj=True)
+                W, Gd = g.links(U, prec), g.gauge(G0)
+                api.sweeps(W, Gd, 3)
+                got.append((g.host_gauge(G), info["traj"], g.host_links(W), g.host_gauge(Gd)))
+            for k, (a, b) in enumerate(zip(*got)):
+                assert np.array_equal(a, b), (hits, exact, k)
+    finally:
+        api.set_paired(True)
+        api.set_update_variant(1, 1)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_sweeps_timed(S, g, api, prec):
     """mcg_sweeps_timed leaves W and G exactly as mcg_sweeps does (ring folds
