@@ -198,14 +198,28 @@ def main(argv=None):
     ap.add_argument("--compare", action="store_true",
                     help="run every configuration in both precisions and report the FP32 - FP64 differences")
     ap.add_argument("--json", action="store_true", help="print the raw per-configuration results as JSON")
+    ap.add_argument("--first", type=int, default=0,
+                    help="index of the first configuration (seeds follow the index, so runs can be split)")
+    ap.add_argument("--jsonl", default=None,
+                    help="append each configuration's results (first precision) to this file, one JSON line each")
+    ap.add_argument("--tables", nargs="+", default=None, metavar="JSONL",
+                    help="print the tables of the configurations recorded in these files and exit (no GPU)")
     a = ap.parse_args(argv)
+    if a.tables:
+        rows = [json.loads(ln) for f in a.tables for ln in open(f) if ln.strip()]
+        seen = {}
+        for r in rows:  # one entry per configuration index, the last one recorded
+            seen[r["config"]] = r["levels"]
+        print(f"{len(seen)} configurations", flush=True)
+        print(format_tables([seen[k] for k in sorted(seen)]), flush=True)
+        return
     L = tuple(int(v) for v in a.lattice.split(","))
     precs = (1, 0) if a.compare else ((1,) if a.prec == "fp32" else (0,))
     results = {p: [] for p in precs}
     lw = a.action == "lw"
     beta = a.beta if a.beta is not None else (4.52 if lw else 5.7)
     therm = a.therm if a.therm is not None else (100 if lw else 50)
-    for c in range(a.configs):
+    for c in range(a.first, a.first + a.configs):
         if lw:
             U64 = synth.heatbath_lw_field_gpu(L, synth.sub_seed(12, c), beta, therm, a.u0)
         else:
@@ -219,6 +233,10 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(f"configuration {c}: " + ", ".join(f"{r['level']}: R {r['R']:.5f} v {r['vortices']}"
                                                  for r in results[precs[0]][-1]), flush=True)
+        if a.jsonl:
+            with open(a.jsonl, "a") as fh:
+                fh.write(json.dumps(dict(config=c, action=a.action, lattice=list(L), beta=beta,
+                                         levels=results[precs[0]][-1])) + "\n")
     for p in precs:
         print(f"\n{'FP32' if p == 1 else 'FP64'} links", flush=True)
         print(json.dumps(results[p]) if a.json else format_tables(results[p]), flush=True)

@@ -70,3 +70,15 @@ def test_paper_levels():
 def test_format_tables_renders():
     text = LV.format_tables(CFG)
     assert "vortex reduction" in text and "higher maximum" in text and "32.5+-10.6" in text
+
+
+def test_tables_from_split_runs(tmp_path, capsys):
+    """Configurations recorded one JSON line each, over two files (a split
+    run, one configuration recorded twice), give the tables of the whole set."""
+    import json
+    a, b = tmp_path / "a.jsonl", tmp_path / "b.jsonl"
+    a.write_text("".join(json.dumps(dict(config=c, levels=CFG[c])) + "\n" for c in (0, 1)))
+    b.write_text("".join(json.dumps(dict(config=c, levels=CFG[c])) + "\n" for c in (1, 2)))
+    LV.main(["--tables", str(a), str(b)])
+    out = capsys.readouterr().out
+    assert out.startswith("3 configurations") and LV.format_tables(CFG) in out
