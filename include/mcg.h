@@ -298,16 +298,20 @@ mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
  * MCG_OPT_SCRATCH_LIMIT_MIB, the call updates G in place instead (the same
  * results) and does not fail. */
 #define MCG_OPT_DEFER_G 9
-/* MCG_OPT_PAIRED (0/1, default 1): where the transform ring is in use (FP32
+/* MCG_OPT_PAIRED (0/1/2, default 1): where the transform ring is in use (FP32
  * links in the two-row form, MCG_OPT_DEFER_G), the first half-sweep of each
  * sweep only records its g in the ring and leaves the links alone; the second
  * applies that pending g of each neighbour to the links it loads, then its
  * own update.  Each link joins one site of each parity, so it is then read
  * twice and written once per sweep instead of read and written twice (with
  * the ring: 648 instead of 816 bytes per site-update, Sec. II.A's sweep
- * unchanged).  Results are bit-identical to 0: both forms apply g to the
- * links with row 2 rebuilt from rows 0 and 1 and in one fixed FMA order.
- * Without the ring the option has no effect. */
+ * unchanged).  2: FP64 fixes and raw sweeps (two-row form) are paired too,
+ * the even g handed over in a one-slot buffer of 48 * L0*L1*L2*L3 bytes per
+ * field (optional like the ring) while G is updated in place: 1440 instead
+ * of 1728 bytes per site-update, but slower on MI355X, where the FP64
+ * half-sweep is bound by its arithmetic at one wave per SIMD.  Results are
+ * bit-identical for all values: every form applies g to the links with row
+ * 2 rebuilt from rows 0 and 1 and in one fixed FMA order. */
 #define MCG_OPT_PAIRED 10
 /* MCG_OPT_CHECK (0/1, default 0): every call that reads links or a gauge
  * transform (smear, apply_gauge, fix, fix_batch, center_project,

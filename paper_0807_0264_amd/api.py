@@ -455,16 +455,18 @@ def get_defer_g(device=None):
 def set_paired(on, device=None):
     """With the transform ring (FP32, two-row form): the first half-sweep of
     each sweep only records its transform, the second applies it to the links
-    as it loads them (bit-identical, each link written once per sweep)."""
+    as it loads them (bit-identical, each link written once per sweep); 2:
+    FP64 sweeps paired too (slower on MI355X)."""
     ctx = context(device)
-    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_PAIRED, 1 if on else 0), ctx)
+    v = 2 if (not isinstance(on, bool) and on == 2) else (1 if on else 0)
+    _check(A.load().mcg_set_option(ctx, A.MCG_OPT_PAIRED, v), ctx)
 
 
 def get_paired(device=None):
     ctx = context(device)
     v = C.c_int32()
     _check(A.load().mcg_get_option(ctx, A.MCG_OPT_PAIRED, C.byref(v)), ctx)
-    return bool(v.value)
+    return v.value
 
 
 def get_sweep_order(device=None):

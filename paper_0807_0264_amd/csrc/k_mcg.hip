@@ -30,16 +30,16 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
                             int gslot, int pend, int keep) {
   const LatDesc<T> *dd = (const LatDesc<T> *)D;
   const int bs = variant_block(variant), g = gated ? 1 : 0;
-  // the paired form needs the two-row working field and a ring slot for the first half's g
+  // the paired form needs the two-row working field and a slot for the first half's g (with the
+  // FP32 ring, that half-sweep's own ring slot)
   if ((pend >= 0 || keep) && !c12) return hipErrorInvalidValue;
-  if ((keep || pend >= 0) && sizeof(T) != 4) return hipErrorInvalidValue;  // the ring holds FP32 g
-  if (keep && (gslot < 0 || pend >= 0 || withR)) return hipErrorInvalidValue;
+  if (keep && (pend < 0 || withR || (gslot >= 0 && gslot != pend))) return hipErrorInvalidValue;
   if (hits > 1 || exact) {  // one instantiation: 256-thread blocks (the caller's descriptors use variant 2)
     if (bs != 256) return hipErrorInvalidValue;
 #define MCG_HM(WR, C, E) \
   k_halfsweep<T, 256, WR, 1, C, true, E><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend, hits)
-    if constexpr (sizeof(T) == 4) {
-      if (keep) {  // the first half of a paired sweep: the links stay, g goes to the ring
+    {
+      if (keep) {  // the first half of a paired sweep: the links stay, g goes to slot pend
 #define MCG_HK(E) \
   k_halfsweep<T, 256, false, 1, true, true, E, KEEP><<<blocks, 256, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend, hits)
         if (exact) MCG_HK(true); else MCG_HK(false);
@@ -80,10 +80,12 @@ hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blo
   MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, false, OCC, true, false, false, KEEP><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend)))
 #define MCG_HP(WR, OCC) \
   MCG_BS_SWITCH(bs, (k_halfsweep<T, BS, WR, OCC, true, false, false, PEND><<<blocks, BS, 0, s>>>(dd, B, par, (T)omega, g, slab, rev, gslot, pend)))
-  if constexpr (sizeof(T) == 4) {
+  {
+    // no link products: FP32 three waves per SIMD without spills (variants 0-2), four with a few
+    // (3-5); FP64 as the variant says
+    constexpr int K1 = sizeof(T) == 4 ? 3 : 1, K2 = sizeof(T) == 4 ? 4 : 2;
     if (keep) {
-      // no link products: three waves per SIMD without spills (variants 0-2), four with a few (3-5)
-      if (variant / 3 == 0) { MCG_HK(3); } else { MCG_HK(4); }
+      if (variant / 3 == 0) { MCG_HK(K1); } else { MCG_HK(K2); }
       return hipGetLastError();
     }
     if (pend >= 0) {

@@ -43,7 +43,7 @@ struct mcg_ctx {
   bool exact = false;  // exact maximisation over each SU(2) subgroup (MCG_OPT_EXACT)
   int order = 2;       // 1: odd half-sweeps visit the tiles in reverse order; 2: and each XCD a contiguous range (MCG_OPT_ORDER)
   bool defer_g = true;  // FP32 fixes keep each half-sweep's g in a ring, folded into G later (MCG_OPT_DEFER_G)
-  bool paired = true;   // with the ring, the first half-sweep of a sweep leaves the links to the second
+  int paired = 1;  // 1: FP32 (ring) sweeps paired, 2: FP64 too (MCG_OPT_PAIRED)
   bool check = false;       // validate input links and transforms (MCG_OPT_CHECK)
   size_t scratch_limit = 0;  // bytes of device scratch the context may hold, 0 = no limit
   size_t scratch_used = 0;
@@ -272,18 +272,24 @@ template <typename T> struct FixRun {
   int C = 0;
   int since_fold = 0;
   bool stateful = true;  // fields carry a FixState (the fold count comes from it)
-  // Paired sweeps (two-row form with the ring): the even half-sweep only records g in its slot,
+  // Paired sweeps (two-row form with the FP32 ring, or FP64 with a one-slot handoff `hand`): the
+  // even half-sweep leaves the links and records g (in its ring slot, or in the handoff slot 0),
   // the odd one applies it to the links it loads.
   bool paired = false;
+  bool hand = false;
 
   mcg_status pass(int par, bool wr, int slab) {
     const int blocks = slab < 0 ? total_blocks : grid[slab];
     const int slot = C ? 2 * since_fold + par : -1;
-    const bool pr = paired && C && c12;
+    const bool pr = paired && c12 && (C || hand);
+    int pend = -1, keep = 0;
+    if (pr) {
+      keep = par == 0 ? 1 : 0;
+      pend = C ? (par == 0 ? slot : slot - 1) : 0;
+    }
     if (blocks > 0)
       HIPCHK(launch_halfsweep<T>(variant, c12, dD, B, blocks, par, omega, wr, gated, s, slab, hits, exact,
-                                 tile_order(order, par), slot, pr && par == 1 ? slot - 1 : -1,
-                                 pr && par == 0 ? 1 : 0));
+                                 tile_order(order, par), slot, pend, keep));
     return MCG_OK;
   }
   // Launched whatever since_fold says on the host: a field's own count decides what is folded,
@@ -405,16 +411,20 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     hS[b] = f;
     total += nb;
   }
-  // the ring last, after everything the fix cannot do without
+  // the ring (or FP64's handoff slot for paired sweeps) last, after everything the fix cannot do
+  // without
   if (ring) ring = reserve_rings(ctx, B, U, gring_sweeps(re));
-  for (int b = 0; b < B && ring; b++) hD[b].gring = (V2<T> *)ctx->gring[b].p;
+  bool hand = prec == MCG_F64 && c12 && ctx->paired == 2;
+  if (hand) hand = reserve_rings(ctx, B, U, 1);
+  for (int b = 0; b < B && (ring || hand); b++) hD[b].gring = (V2<T> *)ctx->gring[b].p;
   FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
   run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
   run.C = ring ? gring_sweeps(re) : 0;
-  run.paired = ctx->paired;
+  run.paired = ctx->paired != 0;
+  run.hand = hand;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
   // the pinned staging area is reused below: wait for these copies first
@@ -880,15 +890,17 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
               (st = ensure(ctx, ctx->g12, gauge_form_bytes(W->d, true)))))
     return st;
   bool ring = parity < 0 && W->prec == MCG_F32 && ctx->defer_g;
-  if (ring) {
+  bool hand = parity < 0 && W->prec == MCG_F64 && c12 && ctx->paired == 2;
+  if (ring || hand) {
     if (ctx->gring.empty()) ctx->gring.resize(1);
-    ring = reserve_rings(ctx, 1, W, GRING_SWEEPS);
+    if (ring) ring = reserve_rings(ctx, 1, W, GRING_SWEEPS);
+    if (hand) hand = reserve_rings(ctx, 1, W, 1);
   }
   // the pinned staging area may still feed an earlier copy on this stream
   HIPCHK(hipStreamSynchronize(s));
   LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
   memset(hD, 0, sizeof(LatDesc<T>));
-  hD->gring = ring ? (V2<T> *)ctx->gring[0].p : nullptr;
+  hD->gring = (ring || hand) ? (V2<T> *)ctx->gring[0].p : nullptr;
   hD->g = g;
   hD->nblk = nb;
   hD->nslab = 1;
@@ -900,7 +912,8 @@ static mcg_status halfsweep_impl(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int p
   run.exact = ctx->exact ? 1 : 0;
   run.order = ctx->order;
   run.C = ring ? GRING_SWEEPS : 0;
-  run.paired = ctx->paired;
+  run.paired = ctx->paired != 0;
+  run.hand = hand;
   run.stateful = false;
   if (parity < 0) run.nslab = plan_slabs(hD, 1, ctx->nslab, variant_block(variant), run.grid);
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>), hipMemcpyHostToDevice, s));
@@ -992,7 +1005,9 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   }
   if (c12 && (st = ensure(ctx, ctx->grad_a, gfull))) return st;
   if (ring) ring = reserve_rings(ctx, B, U, 1);
-  const bool pr = ring && c12 && ctx->paired;  // paired sweeps, as the fixes run them
+  bool hand = prec == MCG_F64 && c12 && ctx->paired == 2;  // FP64 paired sweeps: the even g's handoff slot
+  if (hand) hand = reserve_rings(ctx, B, U, 1);
+  const bool pr = (ring || hand) && c12 && ctx->paired != 0;  // paired sweeps, as the fixes run them
   for (int b = 0; b < B; b++) {
     const Geom g = geom_of(U[b].d);
     if (c12) {
@@ -1027,7 +1042,7 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
         d.nslab = 1;
         d.W = (V2<T> *)ctx->W[b].p;
         d.G = (double2 *)ctx->G12[b].p;
-        d.gring = ring ? (V2<T> *)ctx->gring[b].p : nullptr;
+        d.gring = (ring || hand) ? (V2<T> *)ctx->gring[b].p : nullptr;
         hD[b] = d;
         total += d.nblk;
       }
@@ -1035,13 +1050,13 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
       if (e == hipSuccess) e = hipStreamSynchronize(s);
       for (int k = 0; k < 4 && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr ? 0 : -1,
                                 pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       const int reps = 8;
       for (int k = 0; k < reps && e == hipSuccess; k++)
         e = launch_halfsweep<T>(v, c12, ctx->desc.p, B, total, k & 1, 1.7, false, false, s, -1, 1, 0,
-                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr && (k & 1) ? 0 : -1,
+                                tile_order(ctx->order, k & 1), ring ? (k & 1) : -1, pr ? 0 : -1,
                                 pr && !(k & 1) ? 1 : 0);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1137,8 +1152,8 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
     return MCG_OK;
   }
   if (option == MCG_OPT_PAIRED) {
-    if (value != 0 && value != 1) return fail(ctx, MCG_EINVAL, "MCG_OPT_PAIRED takes 0 or 1");
-    ctx->paired = value != 0;
+    if (value < 0 || value > 2) return fail(ctx, MCG_EINVAL, "MCG_OPT_PAIRED takes 0, 1 or 2");
+    ctx->paired = value;
     return MCG_OK;
   }
   if (option == MCG_OPT_CHECK) {
@@ -1196,7 +1211,7 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
     return MCG_OK;
   }
   if (option == MCG_OPT_PAIRED) {
-    *value = ctx->paired ? 1 : 0;
+    *value = ctx->paired;
     return MCG_OK;
   }
   if (option == MCG_OPT_SCRATCH_LIMIT_MIB) {

@@ -323,14 +323,15 @@ template <typename T> __device__ __forceinline__ M3<T> ring_g(const V2<T> *slot,
 // linearises sum_k |tr(g M_k)|^2 at the current g, X_g = sum_k conj(tr(g M_k)) M_k, and runs
 // the subgroup steps on g X_g, continuing g.  EXACT: each subgroup step instead maximises
 // sum_k |tr(s g M_k)|^2 over its subgroup exactly (then over-relaxes), `hits` rounds of three.
-// Paired sweeps (C12 with the transform ring): the first half-sweep of a sweep leaves the links
-// alone (keep) and only records its g in ring slot gslot; the second (pend = that slot) applies
-// the pending g of each neighbour to the links it loads, exactly as the first half-sweep would
-// have stored them, before its own update.  Every link then joins one site of each parity, so it
+// Paired sweeps (C12): the first half-sweep of a sweep leaves the links alone (KEEP) and records
+// its g in slot pend of d.gring (FP32: its ring slot; FP64: a one-slot handoff, G updated in
+// place as usual); the second (PEND) applies the pending g of each neighbour, read from slot pend,
+// to the links it loads, exactly as the first half-sweep would have stored them, before its own
+// update.  Every link then joins one site of each parity, so it
 // is read twice and written once per sweep instead of read and written twice, and the result is
 // that of two plain half-sweeps bit for bit: the link products in both modes are fixed FMA
 // sequences with row 2 of g rebuilt from rows 0 and 1, the form the ring keeps.
-// MODE: PLAIN, KEEP (first half of a paired sweep) or PEND (second half; pend names the slot).
+// MODE: PLAIN, KEEP (first half of a paired sweep) or PEND (second half); pend names the slot.
 enum { PLAIN = 0, KEEP = 1, PEND = 2 };
 template <typename T, int BS, bool WR, int OCC, bool C12, bool MULTI = false, bool EXACT = false,
           int MODE = PLAIN>
@@ -488,19 +489,30 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
         if (WR) r += tr2(bn);
       }
     }
-    if (keep || gslot >= 0) {
-      // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold); streaming
-      // stores leave the last-level cache to the links that the next half-sweep reads, except
-      // where that half-sweep reads this g (keep)
-      const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
+    const unsigned og = (unsigned)h * (unsigned)sizeof(V2<T>);
+    if (keep) {
+      // the first half of a paired sweep: rows 0 and 1 of g into slot pend, which the second half
+      // reads next (plain stores, so the caches keep them for it); with the FP32 ring that slot is
+      // also this half-sweep's ring slot
 #pragma unroll
       for (int k = 0; k < 6; k++) {
         V2<T> v;
         v.x = g.e[k].re;
         v.y = g.e[k].im;
-        V2<T> *plane = d.gring + ((size_t)gslot * 6 + k) * d.g.Vh;
-        if (keep) st_plane(plane, o, v);
-        else st_plane_stream(plane, o, v);
+        st_plane(d.gring + ((size_t)pend * 6 + k) * d.g.Vh, og, v);
+      }
+    }
+    if (gslot >= 0) {
+      if (!keep || gslot != pend) {
+        // deferred: rows 0 and 1 of g into ring slot gslot, folded into G later (k_fold); streaming
+        // stores leave the last-level cache to the links that the next half-sweep reads
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+          V2<T> v;
+          v.x = g.e[k].re;
+          v.y = g.e[k].im;
+          st_plane_stream(d.gring + ((size_t)gslot * 6 + k) * d.g.Vh, og, v);
+        }
       }
     } else {
       M3<double> gd = m_cvt<double>(g);

@@ -292,7 +292,7 @@ def set_defer_g(on):
 
 
 def set_paired(on):
-    check(lib().mcg_set_option(ctx(), 10, 1 if on else 0))
+    check(lib().mcg_set_option(ctx(), 10, int(on)))
 
 
 def set_check(on):

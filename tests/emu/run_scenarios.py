@@ -284,6 +284,21 @@ def scenario_defer():
     E.set_paired(True)
     E.set_defer_g(True)
     E.set_two_row(True)
+    # FP64 with paired = 2: the even g is handed over in a one-slot buffer, G updated in place
+    U0 = field(L1, 2093)
+    got = []
+    for paired in (2, 1):
+        E.set_paired(paired)
+        Gs = [E.gauge_identity(L2), E.gauge(G1)]
+        infos = E.fix_batch([E.links(field(L2, 2094), 0), E.links(U0, 0)], Gs, [1e-9, -1.0], [40, 40],
+                            reunit_every=30, check_every=5)
+        W, Gd = E.links(U0, 0), E.gauge(G1)
+        E.sweeps(W, Gd, 7)
+        got.append([infos[0]["traj"], infos[1]["traj"], E.host_links(W), E.host_gauge(Gd)]
+                   + [E.host_gauge(x) for x in Gs])
+    for k, (a, b) in enumerate(zip(*got)):
+        check(np.array_equal(a, b), f"FP64 paired sweeps differ from plain ones (item {k})")
+    E.set_paired(True)
 
 
 def expect_error(fn, status_word, what):
@@ -338,8 +353,8 @@ def scenario_checks(prec):
         E.set_scratch_limit_mib(0)
     _, info = E.fix(E.links(U8, prec), None, tol=-1.0, max_sweeps=1)
     check(info["sweeps"] == 1, "usable after the limit")
-    # option values out of range: the tile order takes 0-2, paired sweeps and the ring 0 or 1
-    for opt, val in ((8, 3), (8, -1), (10, 2), (10, -1), (9, 2)):
+    # option values out of range: the tile order and paired sweeps take 0-2, the ring 0 or 1
+    for opt, val in ((8, 3), (8, -1), (10, 3), (10, -1), (9, 2)):
         check(E.lib().mcg_set_option(E.ctx(), opt, val) == -1, f"option {opt} = {val} rejected")
     import ctypes
     v = ctypes.c_int32()

@@ -399,6 +399,37 @@ def test_transform_ring_is_bitwise(S, g, api, two_row):
             assert np.array_equal(a, b), (m, k)
 
 
+def test_paired_sweeps_fp64(S, g, api):
+    """FP64 links with MCG_OPT_PAIRED = 2: paired sweeps (the even g handed to
+    the odd half-sweep in a one-slot buffer, G updated in place) give the bits
+    of plain ones: a batch where one field stops early, a standalone fix and
+    raw sweeps."""
+    prec = 0
+    L1, L2 = (8, 8, 8, 16), (6, 6, 6, 10)
+    U1 = field(S, L1, 1062)
+    U2 = field(S, L2, 1063)
+    G1 = S.haar_gauge(L1, S.sub_seed(1064))
+    got = []
+    try:
+        for paired in (2, 1):
+            api.set_paired(paired)
+            assert api.get_paired() == paired
+            Gb, infos = api.fix_batch([g.links(U2, prec), g.links(U1, prec)],
+                                      [api.gauge_identity(L2), g.gauge(G1)], tol=[1e-4, -1.0],
+                                      max_sweeps=[120, 120], reunit_every=30, check_every=5, want_traj=True)
+            G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=37, reunit_every=50,
+                              check_every=9, want_traj=True)
+            W, Gd = g.links(U1, prec), g.gauge(G1)
+            api.sweeps(W, Gd, 9)
+            got.append([infos[0]["traj"], infos[1]["traj"], infos[0]["sweeps"], g.host_gauge(Gb[0]),
+                        g.host_gauge(Gb[1]), info["traj"], g.host_gauge(G), g.host_links(W), g.host_gauge(Gd)])
+    finally:
+        api.set_paired(True)
+    assert got[0][2] < 120
+    for k, (a, b) in enumerate(zip(*got)):
+        assert np.array_equal(a, b), k
+
+
 def test_paired_sweeps_with_hits_and_exact_steps(S, g, api):
     """FP32 with the ring: paired sweeps give the bits of plain ones also for
     re-linearisation hits and exact subgroup steps (their own 256-thread
