@@ -48,7 +48,8 @@ template <typename T> struct LatDesc {
   int npart;
   double *traj;    // device copy of the R trajectory (max_k + 1) or null
   // ring of per-half-sweep transforms (FP32 fields) or null: slot q holds rows 0 and 1 of the g of
-  // every site of parity q & 1, complex element (q, k < 6, h) at (q*6 + k)*Vh + h
+  // every site of parity q & 1, complex element (q, k < 6, h) at (q*6 + k)*Vh + h; for FP64 fields
+  // with paired sweeps, slot 0 alone: the even g handed to the odd half-sweep
   V2<T> *gring;
 };
 

@@ -17,12 +17,14 @@ inline int variant_block(int v) { return v % 3 == 0 ? 64 : (v % 3 == 1 ? 128 : 2
 template <typename T>
 // slab < 0: the whole of every field (blocks = total); slab >= 0: that slab's chunks (blocks = their total)
 // hits > 1 (re-linearisation hits) or exact (exact subgroup maximisation) requires variant 2
-// (256-thread blocks); rev: tiles in reverse grid order (same results, other visiting order);
-// gslot >= 0: g goes to that slot of each field's transform ring instead of into G (k_fold);
-// paired sweeps (two-row form with the ring): keep = 1 leaves the links as they are (the first
-// half-sweep of a sweep), pend >= 0 names the ring slot whose g the links still wait for (the
-// second half-sweep applies it as it loads them); the first half runs 3 + variant / 3 waves per SIMD
-// (it has no link products), the second 1 + variant / 3 like a plain half-sweep
+// (256-thread blocks); rev: bit 0 tiles in reverse order within each residue class of the grid
+// index mod 8, bit 1 contiguous tile ranges per XCD within each field (same results, other
+// visiting order); gslot >= 0: g goes to that slot of each field's transform ring instead of into
+// G (k_fold); paired sweeps (two-row form): keep = 1 leaves the links as they are (the first
+// half-sweep of a sweep) and writes g to slot pend of d.gring (with the ring, pend = gslot), and
+// pend >= 0 without keep names the slot whose g the links still wait for (the second half-sweep
+// applies it as it loads them); for FP32 the first half runs 3 + variant / 3 waves per SIMD (it
+// has no link products), the second 1 + variant / 3 like a plain half-sweep
 hipError_t launch_halfsweep(int variant, bool c12, const void *D, int B, int blocks, int par, double omega,
                             bool withR, bool gated, hipStream_t s, int slab = -1, int hits = 1, int exact = 0,
                             int rev = 0, int gslot = -1, int pend = -1, int keep = 0);
