@@ -191,7 +191,7 @@ def scenario_slabs(prec):
     E.set_variant(prec, 0)  # 64-thread blocks: 8 blocks per half-sweep of L1, split into 2 or 3 slabs
     ref = None
     for n, order, paired in ((1, 0, 1), (2, 0, 1), (3, 0, 1), (1, 1, 1), (3, 1, 1), (3, 1, 0), (1, 0, 0),
-                             (1, 2, 1), (3, 2, 1)):
+                             (1, 2, 1), (3, 2, 1), (3, 2, 2), (1, 1, 2)):
         E.set_slabs(n)
         E.set_sweep_order(order)
         E.set_paired(paired)

@@ -326,18 +326,20 @@ def test_synth_gpu_is_bitwise_cpu(S, g):
 @pytest.mark.parametrize("prec", PRECS)
 def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
     """Half-sweeps run slab by slab (several slab counts, a batch mixing a
-    split and an unsplit field), and odd half-sweeps in reverse tile order
-    (also with contiguous tile ranges per XCD), give the bits of whole
-    forward half-sweeps."""
+    split and an unsplit field), odd half-sweeps in reverse tile order (also
+    with contiguous tile ranges per XCD), and paired or plain sweeps (FP64
+    paired too), give the bits of whole forward half-sweeps."""
     L1, L2 = (8, 8, 8, 32), (6, 6, 6, 10)
     U1 = g.rounded(field(S, L1, 1050), prec)
     U2 = g.rounded(field(S, L2, 1051), prec)
     G1 = S.haar_gauge(L1, S.sub_seed(1052))
     ref = None
     try:
-        for n, order in ((1, False), (2, False), (5, False), (8, False), (1, True), (5, True), (1, 2), (5, 2)):
+        for n, order, paired in ((1, False, 1), (2, False, 1), (5, False, 1), (8, False, 1), (1, True, 1),
+                                 (5, True, 1), (1, 2, 1), (5, 2, 1), (5, 2, 2), (1, 1, 0)):
             api.set_slabs(n)
             api.set_sweep_order(order)
+            api.set_paired(paired)
             assert api.get_sweep_order() == order
             G, info = api.fix(g.links(U1, prec), g.gauge(G1), tol=-1.0, max_sweeps=60, reunit_every=25,
                               check_every=20, want_traj=True)
@@ -353,10 +355,11 @@ def test_slab_pipelined_sweeps_are_bitwise(S, g, api, prec):
                 assert np.array_equal(got[1], got[3]) and np.array_equal(got[0], got[4])
             else:
                 for a, b in zip(got, ref):
-                    assert np.array_equal(a, b), (n, order)
+                    assert np.array_equal(a, b), (n, order, paired)
     finally:
         api.set_slabs(1)
         api.set_sweep_order(2)
+        api.set_paired(1)
 
 
 @pytest.mark.parametrize("two_row", [True, False])
