@@ -335,6 +335,13 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
                     ("paired sweeps, g to the transform ring" if paired else "g to the transform ring")
                     if defer else "G updated in place"),
                 ms_per_launch=round(ms, 4), bytes_per_launch=site_updates * bps, bytes_per_site_update=bps,
+                **({"plain_equivalent": dict(
+                    bytes_per_site_update=BYTES_PER_SITE_UPDATE[(two_row, defer)],
+                    GBps=round(site_updates * BYTES_PER_SITE_UPDATE[(two_row, defer)] / (ms * 1e-3) / 1e9, 1),
+                    frac=round(site_updates * BYTES_PER_SITE_UPDATE[(two_row, defer)] / (ms * 1e-3) / 1e9
+                               / HBM_PEAK_GBS, 4),
+                    note="context only: the same time per site-update against the bytes a plain half-sweep "
+                         "with the ring needs (each link written in both half-sweeps)")} if paired else {}),
                 sweep_loop=dict(ms_per_half_sweep=round(loop_ms, 4), bytes_per_site_update=loop_bps,
                                 GBps=round(site_updates * loop_bps / (loop_ms * 1e-3) / 1e9, 1),
                                 note="api.sweeps end to end (conversions of W and G to and from the "
