@@ -77,22 +77,16 @@ __global__ __launch_bounds__(256) void k_loss_seed(Geom g, const V2<T> *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Blocks are dealt to the eight XCDs in turn; within one grid row the blocks of one XCD (equal
-// blockIdx.x mod 8) take a contiguous range of its n tiles instead of every eighth, so a site's
-// neighbours a few tiles away mostly lie on the same XCD and its L2.  Per-block partial sums are
-// stored by tile, so their summation order does not depend on the mapping.
-__device__ __forceinline__ int adj_tile(int i, int n) {
-  const int x = i & 7, q = n >> 3, r = n & 7;
-  return x * q + (x < r ? x : r) + (i >> 3);
-}
-
+// The adjoint kernels map blockIdx.x through xcd_range within each grid row (one row per
+// direction and parity), so a site's neighbours mostly share an XCD's L2; per-block partial sums
+// are stored by tile, so their summation order does not depend on the mapping.
 // --------------------------------------------------------------- pass A
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gOut, V2<T> *__restrict__ gU,
                                                     V2<T> *__restrict__ gC, T rho, T wp, T wr, double *part,
                                                     int *flag) {
-  const int tile = adj_tile((int)blockIdx.x, (int)gridDim.x);
+  const int tile = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = tile * 128 + threadIdx.x;
   const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
   double drho = 0.0, deps = 0.0;
@@ -176,7 +170,7 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
 template <typename T>
 __global__ __launch_bounds__(128) void k_eps_rect(Geom g, const V2<T> *__restrict__ U,
                                                   const V2<T> *__restrict__ gC, T rho, double *part) {
-  const int tile = adj_tile((int)blockIdx.x, (int)gridDim.x);
+  const int tile = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = tile * 128 + threadIdx.x;
   const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
   double deps = 0.0;
@@ -316,7 +310,7 @@ __device__ __forceinline__ void path_terms(const Geom &g, const Links<T> &L, con
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
-  const int h = adj_tile((int)blockIdx.x, (int)gridDim.x) * 128 + threadIdx.x;
+  const int h = xcd_range((int)blockIdx.x, (int)gridDim.x) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
   const int lnu = blockIdx.y >> 1, par = blockIdx.y & 1;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh}, GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};

@@ -197,6 +197,15 @@ __device__ __forceinline__ void coords_of(const Geom &g, int par, int h, int c[4
   c[2] = z;
   c[3] = t;
 }
+// Workgroups are dealt to the eight XCDs in turn (block i to XCD i mod 8).  xcd_range maps block i
+// of a range of n tiles so that the blocks of one XCD (equal i mod 8) take a contiguous range of
+// tiles, the j-th block of the class (i = class + 8j) the j-th tile of that range, instead of every
+// eighth tile: the tiles a site's neighbours lie in, a few tiles away, then mostly belong to the
+// same XCD and meet in its L2.  A bijection of [0, n) for every n.
+__device__ __forceinline__ int xcd_range(int i, int n) {
+  const int x = i & 7, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
 __device__ __forceinline__ int lex_index(const Geom &g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }

@@ -79,7 +79,8 @@ __global__ __launch_bounds__(256) void k_line(Geom g, const V2<T> *__restrict__ 
   const LoopImage<T> &im = imgs[blockIdx.y];
   const int nbp = gridDim.x >> 1;
   const int par = blockIdx.x >= nbp;
-  const int h = (blockIdx.x - par * nbp) * 256 + threadIdx.x;
+  // tiles of one parity in contiguous ranges per XCD (xcd_range)
+  const int h = xcd_range((int)blockIdx.x - par * nbp, nbp) * 256 + threadIdx.x;
   if (h >= g.Vh) return;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
   const V2<T> *in = k == 1 ? nullptr : ((k & 1) ? im.b : im.a);
@@ -123,7 +124,9 @@ __global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ 
   const int D0 = k * im.path.d[0], D1 = k * im.path.d[1], D2 = k * im.path.d[2];
   const int nbp = gridDim.x >> 1;
   const int par = blockIdx.x >= nbp;
-  const int h = (blockIdx.x - par * nbp) * BS + threadIdx.x;
+  // tiles of one parity in contiguous ranges per XCD (xcd_range); the block sums are stored by tile
+  const int tile = par * nbp + xcd_range((int)blockIdx.x - par * nbp, nbp);
+  const int h = (tile - par * nbp) * BS + threadIdx.x;
   const bool live = h < g.Vh;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
   const Links<T> Sf{const_cast<V2<T> *>(S), g.Vh};
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(BS) void k_wloop(Geom g, const V2<T> *__restrict__ 
         val += (double)P.e[q].re * (double)Q.e[q].re + (double)P.e[q].im * (double)Q.e[q].im;
     }
     const double s = block_sum<BS>(val);
-    if (threadIdx.x == 0) pt[(size_t)(t - 1) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) pt[(size_t)(t - 1) * gridDim.x + tile] = s;
   }
 }
 

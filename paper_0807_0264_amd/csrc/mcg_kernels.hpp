@@ -32,15 +32,10 @@ __device__ __forceinline__ int tile_of_block(int rev) {
   return x + 8 * (cx - 1 - (b >> 3));
 }
 
-// rev & 2: within each field's n blocks (or its chunk of a slab), the blocks i of one class
-// i mod 8 (one XCD) take a contiguous range of tiles, the j-th block of the class (i = class + 8j)
-// the j-th tile of the range, instead of every eighth tile; the tiles a site's neighbours lie in,
-// a few tiles away along z, are then mostly handled by the same XCD and meet in its L2.  Applied
-// after the reversal above, it keeps every tile on one XCD in both directions.
-__device__ __forceinline__ int xcd_range(int i, int n) {
-  const int x = i & 7, q = n >> 3, r = n & 7;
-  return x * q + (x < r ? x : r) + (i >> 3);
-}
+// rev & 2: within each field's n blocks (or its chunk of a slab), xcd_range gives the blocks of
+// one XCD a contiguous range of tiles, so a site's neighbours a few tiles away along z mostly lie
+// on the same XCD and meet in its L2.  Applied after the reversal above, it keeps every tile on
+// one XCD in both directions.
 
 template <typename T>
 __device__ __forceinline__ int block_of(const LatDesc<T> *__restrict__ D, int B, int slab, int rev, int &local) {

@@ -9,7 +9,10 @@ namespace mcg {
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__ U,
                                                V2<T> *__restrict__ out, T rho, T wp, T wr) {
-  const int h = blockIdx.x * 128 + threadIdx.x;
+  // stout: tiles of one grid row (one direction and parity) in contiguous ranges per XCD
+  // (xcd_range), 5 % faster at 32^3x64; over-improved (43 links per staple sum): 3 % slower that
+  // way, so in grid order
+  const int h = (OI ? (int)blockIdx.x : xcd_range((int)blockIdx.x, (int)gridDim.x)) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
   const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
