@@ -531,7 +531,10 @@ __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ 
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
-  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  // the field's tiles in contiguous ranges per XCD (xcd_range: the forward neighbours' G share an
+  // L2); the partial sums are stored by tile, in the same order as ever
+  const int lb = xcd_range((int)blockIdx.x - d.blk0, d.nblk);
+  const int h = lb * BS + (int)threadIdx.x;
   double r = 0.0;
   if (h < d.g.Vh) {
     const WS W{d.W, d.g.Vh};
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(BS) void k_rederive(const LatDesc<T> *__restrict__ 
     }
   }
   const double s = wave_sum(r);
-  if ((threadIdx.x & 63) == 0) d.part[((int)blockIdx.x - d.blk0) * (BS / 64) + (threadIdx.x >> 6)] = s;
+  if ((threadIdx.x & 63) == 0) d.part[lb * (BS / 64) + (threadIdx.x >> 6)] = s;
 }
 
 // G <- g_{n-1} ... g_1 g_0 G for the transforms g_j that the half-sweeps of each parity left in
