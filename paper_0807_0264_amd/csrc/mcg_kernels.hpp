@@ -570,7 +570,8 @@ __global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, i
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   const int n = d.st ? d.st->k - d.st->kfold : nfix;
-  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  // the field's tiles in contiguous ranges per XCD (xcd_range), as the half-sweeps take them
+  const int h = xcd_range((int)blockIdx.x - d.blk0, d.nblk) * BS + (int)threadIdx.x;
   if (h >= d.g.Vh || n <= 0 || !d.gring) return;
   const GS G{d.G, d.g.Vh};
   const unsigned o = (unsigned)h * (unsigned)sizeof(V2<T>);
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(BS) void k_reunit(const LatDesc<T> *__restrict__ D,
   const int b = find_field(D, B);
   const LatDesc<T> d = D[b];
   if (gated && d.st->done) return;
-  const int h = ((int)blockIdx.x - d.blk0) * BS + (int)threadIdx.x;
+  const int h = xcd_range((int)blockIdx.x - d.blk0, d.nblk) * BS + (int)threadIdx.x;  // as k_fold
   if (h >= d.g.Vh) return;
   const GS G{d.G, d.g.Vh};
   for (int par = 0; par < 2; par++) {
