@@ -1045,9 +1045,11 @@ void or_step_jvp(const int32_t L[4], const ocx *U, const ocx *dU, double rho,
  *   grad_U += grad_Omega^dag C,  grad_C = grad_Omega U
  *   each factor V_j of a path gets w (V_1..V_{j-1})^dag grad_C (V_{j+1}..V_k)^dag
  *   (its dagger when the path walks the link backwards)
- *   dL/drho = sum <grad_C, C/rho>,  dL/deps = sum <grad_C, rho(-2/3 Cp + 1/12 Cr)> */
+ *   dL/drho = sum <grad_C, C/rho>,  dL/deps = sum <grad_C, rho(-2/3 Cp + 1/12 Cr)>
+ * absEps (nullable): sum over links of |<grad_C, rho(-2/3 Cp + 1/12 Cr)>|, the size of the
+ * terms whose sum is dL/deps (they largely cancel, so this, not dL/deps, scales its rounding) */
 void or_step_vjp(const int32_t L[4], const ocx *U, const ocx *gOut,
-                 double rho, double eps, ocx *gU, double *dRho, double *dEps) {
+                 double rho, double eps, ocx *gU, double *dRho, double *dEps, double *absEps) {
   lat_t lt = mklat(L);
   double wp, wr;
   weights(eps, &wp, &wr);
@@ -1138,16 +1140,22 @@ void or_step_vjp(const int32_t L[4], const ocx *U, const ocx *gOut,
     }
   *dRho = kahan(dr, nl);
   *dEps = kahan(de, nl);
+  if (absEps) {
+    for (int64_t q = 0; q < nl; q++) de[q] = fabs(de[q]);
+    *absEps = kahan(de, nl);
+  }
   free(gC);
   free(dr);
   free(de);
 }
 
 /* Gradient of L = R(S_n(U)^G*) at fixed G*.  With ckpt_every > 0 only every
- * ckpt_every-th smeared field is kept and the others are recomputed. */
+ * ckpt_every-th smeared field is kept and the others are recomputed.  absEps
+ * (nullable): the sum over steps and links of the magnitudes of the terms of
+ * dL/deps (see or_step_vjp). */
 void or_smear_loss_grad(const int32_t L[4], const ocx *U, double rho,
                         double eps, int n, const ocx *Gstar, int ckpt_every,
-                        ocx *gradU, double *dRho, double *dEps, double *loss) {
+                        ocx *gradU, double *dRho, double *dEps, double *loss, double *absEps) {
   lat_t lt = mklat(L);
   int64_t nl = 4 * lt.V;
   size_t bytes = (size_t)nl * 9 * sizeof(ocx);
@@ -1184,7 +1192,7 @@ void or_smear_loss_grad(const int32_t L[4], const ocx *U, double rho,
       }
     free(W);
   }
-  double drho = 0, deps = 0;
+  double drho = 0, deps = 0, aeps = 0;
   ocx *seg = malloc(bytes), *gnew = malloc(bytes);
   for (int k = n - 1; k >= 0; k--) {
     /* rebuild S_k from the nearest checkpoint at or below k */
@@ -1194,15 +1202,17 @@ void or_smear_loss_grad(const int32_t L[4], const ocx *U, double rho,
       or_smear_step(L, seg, nxt, rho, eps);
       memcpy(seg, nxt, bytes);
     }
-    double dr, de;
-    or_step_vjp(L, seg, g, rho, eps, gnew, &dr, &de);
+    double dr, de, ae;
+    or_step_vjp(L, seg, g, rho, eps, gnew, &dr, &de, &ae);
     drho += dr;
     deps += de;
+    aeps += ae;
     memcpy(g, gnew, bytes);
   }
   memcpy(gradU, g, bytes);
   *dRho = drho;
   *dEps = deps;
+  if (absEps) *absEps = aeps;
   for (int q = 0; q < nck; q++) free(ck[q]);
   free(ck);
   free(cur);

@@ -129,12 +129,12 @@ double or_smear_loss(const int32_t L[4], const ocx *U, double rho, double eps,
                      int n, const ocx *Gstar);
 void or_smear_loss_grad(const int32_t L[4], const ocx *U, double rho,
                         double eps, int n, const ocx *Gstar, int ckpt_every,
-                        ocx *gradU, double *dRho, double *dEps, double *loss);
+                        ocx *gradU, double *dRho, double *dEps, double *loss, double *absEps);
 /* one smearing step: tangent (forward mode) and cotangent (reverse mode) */
 void or_step_jvp(const int32_t L[4], const ocx *U, const ocx *dU, double rho,
                  double eps, ocx *dOut);
 void or_step_vjp(const int32_t L[4], const ocx *U, const ocx *gOut,
-                 double rho, double eps, ocx *gU, double *dRho, double *dEps);
+                 double rho, double eps, ocx *gU, double *dRho, double *dEps, double *absEps);
 
 #ifdef __cplusplus
 }

@@ -76,9 +76,9 @@ def _declare(l):
         "or_wilson_path": (C.c_double, [_I4, _P, _P, C.c_int, C.c_int]),
         "or_smear_loss": (C.c_double, [_I4, _P, C.c_double, C.c_double, C.c_int, _P]),
         "or_smear_loss_grad": (None, [_I4, _P, C.c_double, C.c_double, C.c_int, _P, C.c_int,
-                                      _P, _P, _P, _P]),
+                                      _P, _P, _P, _P, _P]),
         "or_step_jvp": (None, [_I4, _P, _P, C.c_double, C.c_double, _P]),
-        "or_step_vjp": (None, [_I4, _P, _P, C.c_double, C.c_double, _P, _P, _P]),
+        "or_step_vjp": (None, [_I4, _P, _P, C.c_double, C.c_double, _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(l, name)
@@ -379,15 +379,19 @@ def smear_loss(U, rho, eps, n, Gstar):
     return lib().or_smear_loss(_dims(dims_of(U)), _ptr(U), rho, eps, int(n), _ptr(Gstar))
 
 
-def smear_loss_grad(U, rho, eps, n, Gstar, ckpt_every=0):
+def smear_loss_grad(U, rho, eps, n, Gstar, ckpt_every=0, want_eps_scale=False):
+    """(gradU, dL/drho, dL/deps, L); with want_eps_scale also the sum over steps
+    and links of the magnitudes of the terms that add up to dL/deps."""
     U, Gstar = _c128(U), _c128(Gstar)
     g = np.empty_like(U)
     dr = np.zeros(1)
     de = np.zeros(1)
     loss = np.zeros(1)
+    ae = np.zeros(1)
     lib().or_smear_loss_grad(_dims(dims_of(U)), _ptr(U), rho, eps, int(n), _ptr(Gstar),
-                             int(ckpt_every), _ptr(g), _ptr(dr), _ptr(de), _ptr(loss))
-    return g, float(dr[0]), float(de[0]), float(loss[0])
+                             int(ckpt_every), _ptr(g), _ptr(dr), _ptr(de), _ptr(loss), _ptr(ae))
+    out = (g, float(dr[0]), float(de[0]), float(loss[0]))
+    return out + (float(ae[0]),) if want_eps_scale else out
 
 
 def step_jvp(U, dU, rho, eps):
@@ -403,5 +407,5 @@ def step_vjp(U, gOut, rho, eps):
     dr = np.zeros(1)
     de = np.zeros(1)
     lib().or_step_vjp(_dims(dims_of(U)), _ptr(U), _ptr(gOut), rho, eps, _ptr(gU),
-                      _ptr(dr), _ptr(de))
+                      _ptr(dr), _ptr(de), None)
     return gU, float(dr[0]), float(de[0])

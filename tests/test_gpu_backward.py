@@ -33,13 +33,18 @@ def test_backward_vs_oracle(S, O, env, L, prec, rho, eps, n, ck):
     U = g.rounded(S.heatbath_field(L, S.sub_seed(3000), 5.7, 5), prec)
     G = S.haar_gauge(L, S.sub_seed(3001))
     grad, loss, dr, de = api.smear_mcg_backward(g.links(U, prec), rho, eps, n, g.gauge(G), ck)
-    go, dro, deo, losso = O.smear_loss_grad(U, rho, eps, n, G, ckpt_every=ck)
+    go, dro, deo, losso, scale = O.smear_loss_grad(U, rho, eps, n, G, ckpt_every=ck, want_eps_scale=True)
     tol = 1e-11 if prec == 0 else 1e-5
     assert np.abs(g.host_links(grad) - go).max() < tol * np.abs(go).max()
     assert abs(loss - losso) < tol * losso
     assert abs(dr - dro) < tol * abs(dro)
-    # dL/deps can be a near-cancellation of terms of the size of dL/drho
-    assert abs(de - deo) < tol * max(abs(deo), abs(dro))
+    # dL/deps is a sum over steps and links of terms that cancel to 1/60 - 1/2400 of their summed
+    # magnitude `scale` here.  FP64: relative to dL/deps itself.  FP32: every term to the FP32 bar,
+    # i.e. the error within tol times the summed magnitude of the terms (rounding of a term is
+    # relative to that term, and a sum cannot undo it).
+    print(f"dL/deps {deo:.3e}, terms {scale:.3e}, |error| {abs(de - deo):.2e} "
+          f"({abs(de - deo) / abs(deo):.2e} of dL/deps, {abs(de - deo) / scale:.2e} of the terms)")
+    assert abs(de - deo) < (tol * abs(deo) if prec == 0 else tol * scale)
 
 
 def test_backward_oi20_vs_oracle_6x4(S, O, env):
@@ -52,7 +57,9 @@ def test_backward_oi20_vs_oracle_6x4(S, O, env):
     grad, loss, dr, de = api.smear_mcg_backward(g.links(U, 0), 0.06, -0.25, 20, g.gauge(G), 5)
     go, dro, deo, losso = O.smear_loss_grad(U, 0.06, -0.25, 20, G, ckpt_every=5)
     assert np.abs(g.host_links(grad) - go).max() < 1e-11 * np.abs(go).max()
-    assert abs(dr - dro) < 1e-11 * abs(dro) and abs(de - deo) < 1e-11 * max(abs(deo), 1e-6)
+    print(f"dL/drho {dro:.3e} dL/deps {deo:.3e}: relative errors {abs(dr - dro) / abs(dro):.2e}, "
+          f"{abs(de - deo) / abs(deo):.2e}")
+    assert abs(dr - dro) < 1e-11 * abs(dro) and abs(de - deo) < 1e-11 * abs(deo)
 
 
 @pytest.fixture(scope="module")
@@ -79,8 +86,10 @@ def test_c4_finite_differences_fp64(S, env, c4):
     assert abs(loss - _loss(api, U, rho, eps, n, G)) < 1e-14
     fd_rho = _fd(lambda s: _loss(api, U, rho + s, eps, n, G), h)
     fd_eps = _fd(lambda s: _loss(api, U, rho, eps + s, n, G), h)
+    print(f"C4: dL/drho {dr:.6e} (FD {fd_rho:.6e}), dL/deps {de:.6e} (FD {fd_eps:.6e}): relative "
+          f"{abs(fd_rho - dr) / abs(dr):.2e}, {abs(fd_eps - de) / abs(de):.2e}")
     assert abs(fd_rho - dr) <= 1e-6 * abs(dr)
-    assert abs(fd_eps - de) <= 1e-6 * max(abs(de), 1e-3)
+    assert abs(fd_eps - de) <= 1e-6 * abs(de)
     # random su(3) tangent: U_l -> exp(h X_l) U_l
     X = S.su3_tangent(L, S.sub_seed(3003))
     Uh = U64.cpu().numpy()

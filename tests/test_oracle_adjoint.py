@@ -78,8 +78,19 @@ def test_jvp_matches_finite_difference(O, S):
 
 def test_rho_zero_gives_zero_eps_derivative(O, setup):
     U, G = setup
-    _, drho, deps, _ = O.smear_loss_grad(U, 0.0, -0.25, 2, G)
-    assert deps == 0.0
+    _, drho, deps, _, scale = O.smear_loss_grad(U, 0.0, -0.25, 2, G, want_eps_scale=True)
+    assert deps == 0.0 and scale == 0.0
+
+
+def test_eps_term_scale_bounds_the_derivative(O, setup):
+    """The summed magnitude of the terms of dL/deps bounds |dL/deps| (triangle inequality) and
+    does not depend on checkpointing; the gradient itself is unchanged by asking for it."""
+    U, G = setup
+    a = O.smear_loss_grad(U, 0.06, -0.25, 4, G, ckpt_every=2, want_eps_scale=True)
+    b = O.smear_loss_grad(U, 0.06, -0.25, 4, G, ckpt_every=0, want_eps_scale=True)
+    c = O.smear_loss_grad(U, 0.06, -0.25, 4, G, ckpt_every=2)
+    assert a[4] >= abs(a[2]) > 0 and a[4] == b[4]
+    assert np.array_equal(a[0], c[0]) and a[1:4] == c[1:4]
 
 
 def test_checkpointing_is_bitwise(O, setup):

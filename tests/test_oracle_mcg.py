@@ -146,3 +146,46 @@ def test_max_sweeps_reports_not_converged(O, U):
     G, info, _ = O.mcg_fix(U, tol=1e-12, max_sweeps=1)
     assert info["status"] == 1 and info["sweeps"] == 1
     assert unitarity_error(G) < 1e-14
+
+
+def _one_link_field(L, x0, alpha, beta):
+    """Unit links except U_0 at site x0 = diag(e^{i a}, e^{i b}, e^{-i(a+b)})."""
+    U = np.zeros(tuple(L[::-1]) + (4, 3, 3), np.complex128)
+    U[..., :, 0, 0] = U[..., :, 1, 1] = U[..., :, 2, 2] = 1
+    d = np.exp(1j * np.array([alpha, beta, -alpha - beta]))
+    U[x0[3], x0[2], x0[1], x0[0], 0] = np.diag(d)
+    return U, d
+
+
+def test_theta_closed_form_one_link(O):
+    """theta = (1/V) sum_x |TA X(x)|^2.  With every link 1 except one diagonal D = U_0(x0), X is a
+    multiple of 1 except at x0 (X = 21 + conj(t) D, t = tr D) and at x0 + 0 (X = 21 + t D^dagger);
+    TA of a diagonal A is i(Im A_kk - mean_j Im A_jj) on the diagonal, and Im(t conj d_k) =
+    -Im(conj(t) d_k), so theta = (2/V) sum_k (Im(conj(t) d_k) - mean)^2."""
+    L = (4, 2, 2, 2)
+    U, d = _one_link_field(L, (1, 0, 1, 0), 0.7, -0.2)
+    t = d.sum()
+    im = (np.conj(t) * d).imag
+    want = 2 * np.sum((im - im.mean()) ** 2) / np.prod(L)
+    assert abs(O.theta(U) - want) < 1e-15 and want > 0.1
+    # a pure centre field is stationary
+    assert O.theta(center_links(np.ones((2, 2, 2, 2, 4)))) == 0.0
+
+
+def test_site_g_at_closed_form(O, S):
+    """A unit field with one site x0 transformed by h^dagger: the eight links the update gathers at
+    x0 are all M_k = h^dagger (forward g(x0) 1, backward (1 g(x0)^dagger)^dagger), so the
+    linearisation is X = 8 tr(h) h^dagger.  For h in the (0, 1) subgroup with tr h > 0 the (0, 1)
+    step at omega = 1 maximises Re tr(s X) at s = h, and the other two steps then see a multiple of
+    1: the update is g = h exactly, which takes the site back to the unit field."""
+    L = (4, 4, 2, 2)
+    a = np.array([0.6, 0.3, -0.5, 0.2])
+    a /= np.linalg.norm(a)
+    h = np.eye(3, dtype=np.complex128)
+    h[:2, :2] = [[a[0] + 1j * a[3], a[2] + 1j * a[1]], [-a[2] + 1j * a[1], a[0] - 1j * a[3]]]
+    g = np.tile(np.eye(3, dtype=np.complex128), tuple(L[::-1]) + (1, 1))
+    x0 = (2, 1, 1, 0)
+    g[x0[3], x0[2], x0[1], x0[0]] = dag(h)
+    U = gauge_transform(center_links(np.zeros(tuple(L[::-1]) + (4,))), g)
+    i = x0[0] + L[0] * (x0[1] + L[1] * (x0[2] + L[2] * x0[3]))
+    assert np.abs(O.site_g_at(U, i, 1.0) - h).max() < 1e-14

@@ -172,3 +172,38 @@ def test_vortex_fields(O, S):
     # without G the removal acts on U itself
     Z0, _ = O.center_project(U, None)
     assert np.abs(O.vortex_field(U, None, Z0, O.VORTEX_REMOVED) - np.conj(np.exp(2j * np.pi * Z0 / 3))[..., None, None] * U).max() < 1e-15
+
+
+def test_polyakov_abelian_flux_closed_form(O):
+    """The time-like links of the flux field are diag(e^{i th}, e^{i th}, e^{-2 i th}) with
+    th = sum_j 2 pi n_j c_j / (L_j L_t) at every t, so the line through spatial site
+    (x, y, z) has phase phi = sum_j 2 pi n_j c_j / L_j and tr/3 = (2 e^{i phi} + e^{-2 i phi}) / 3.
+    A walk along a spatial axis, a wrong site index or a daggered product fails it (the
+    value is complex and differs from site to site)."""
+    L, n = L_FLUX, N_FLUX
+    P = O.polyakov(flux_field(L, n))
+    for z in range(L[2]):
+        for y in range(L[1]):
+            for x in range(L[0]):
+                phi = 2 * np.pi * (n[0] * x / L[0] + n[1] * y / L[1] + n[2] * z / L[2])
+                want = (2 * np.exp(1j * phi) + np.exp(-2j * phi)) / 3
+                assert abs(P[x + L[0] * (y + L[1] * z)] - want) < 1e-13, (x, y, z)
+    assert np.abs(P.imag).max() > 0.1
+
+
+def test_polyakov_pure_gauge_line_telescopes(O, S):
+    """Time-like links g(t) g(t+1)^dagger (Haar g, spatial links random) multiply to
+    g(0) g(0)^dagger = 1 only when the factors are taken in the order of increasing t:
+    the line is 1 at every spatial site.  Multiplied by a centre element z_t per time
+    slice, the line is the product of the z_t."""
+    L = (4, 2, 2, 6)
+    U = S.haar_links(L, S.sub_seed(4007))
+    g = S.haar_gauge(L, S.sub_seed(4008))
+    gn = np.roll(g, -1, axis=0)
+    U[..., 3, :, :] = g @ np.conj(np.swapaxes(gn, -1, -2))
+    P = O.polyakov(U)
+    assert np.abs(P - 1).max() < 1e-13
+    m = np.array([1, 0, 2, 1, 1, 0])
+    U[..., 3, :, :] *= np.exp(2j * np.pi * m / 3)[:, None, None, None, None, None]
+    want = np.exp(2j * np.pi * m.sum() / 3)
+    assert np.abs(O.polyakov(U) - want).max() < 1e-13
