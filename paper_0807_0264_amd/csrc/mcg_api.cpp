@@ -3,6 +3,7 @@
 // fixing iteration (direct launches for a single field, a captured hipGraph
 // per block of sweeps for batches) and the block-size autotuner.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -52,6 +53,15 @@ struct mcg_ctx {
 };
 
 namespace {
+
+// A ROCTX range around one call of the ABI (smear, fix, fix_batch, projection, counting, backward,
+// Wilson loops), so that a trace groups the kernels of a call under its name.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 mcg_status fail(mcg_ctx *ctx, mcg_status s, const char *fmt, ...) {
   if (ctx) {
@@ -750,6 +760,7 @@ mcg_status mcg_unitarity(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, d
 
 mcg_status mcg_smear(mcg_ctx *ctx, const mcg_field *U, mcg_field *out, double rho, double eps, int32_t n,
                      void *stream) {
+  const Range range_("mcg_smear");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, out, "out"))) return st;
@@ -1096,6 +1107,7 @@ mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant,
 
 mcg_status mcg_autotune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, int32_t *best_variant,
                               double *ms_per_halfsweep, void *stream) {
+  const Range range_("mcg_autotune_batch");
   if (!ctx) return MCG_EINVAL;
   if (B < 1) return fail(ctx, MCG_EINVAL, "batch size %d < 1", B);
   if (!U) return fail(ctx, MCG_EINVAL, "NULL argument");
@@ -1227,6 +1239,7 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value) {
 
 mcg_status mcg_sweeps_timed(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega,
                             double *ms_halfsweeps, void *stream) {
+  const Range range_("mcg_sweeps_timed");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, W, "W")) || (st = check_gauge(ctx, G, W->d, "G"))) return st;
@@ -1239,6 +1252,7 @@ mcg_status mcg_sweeps_timed(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n,
 }
 
 mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, double omega, void *stream) {
+  const Range range_("mcg_sweeps");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, W, "W")) || (st = check_gauge(ctx, G, W->d, "G"))) return st;
@@ -1251,6 +1265,7 @@ mcg_status mcg_sweeps(mcg_ctx *ctx, mcg_field *W, mcg_gauge *G, int32_t n, doubl
 
 mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix_opts *opts,
                    mcg_fix_result *res, void *stream) {
+  const Range range_("mcg_fix");
   if (!ctx) return MCG_EINVAL;
   if (!U) return fail(ctx, MCG_EINVAL, "U is NULL");
   hipStream_t s = (hipStream_t)stream;
@@ -1260,6 +1275,7 @@ mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix
 
 mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge *G,
                          const mcg_fix_opts *opts, mcg_fix_result *res, void *stream) {
+  const Range range_("mcg_fix_batch");
   if (!ctx) return MCG_EINVAL;
   if (!U || B < 1) return fail(ctx, MCG_EINVAL, "empty batch");
   hipStream_t s = (hipStream_t)stream;
@@ -1269,6 +1285,7 @@ mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge 
 
 mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, int8_t *Z,
                               double *min_margin, void *stream) {
+  const Range range_("mcg_center_project");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, U, "U"))) return st;
@@ -1295,6 +1312,7 @@ mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge 
 
 mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t *total, int64_t *per_plane,
                               int64_t *per_charge, void *stream) {
+  const Range range_("mcg_count_vortices");
   if (!ctx) return MCG_EINVAL;
   if (!Z || !total) return fail(ctx, MCG_EINVAL, "NULL argument");
   if (!dims_valid(d)) return fail(ctx, MCG_EINVAL, "bad extents");
@@ -1325,6 +1343,7 @@ mcg_status mcg_count_vortices(mcg_ctx *ctx, const int8_t *Z, mcg_dims d, int64_t
 
 mcg_status mcg_vortex_field(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, const int8_t *Z, int32_t mode,
                             mcg_field *out, void *stream) {
+  const Range range_("mcg_vortex_field");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, out, "out"))) return st;
@@ -1465,6 +1484,7 @@ extern "C" {
 
 mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, const int32_t *vec, int32_t rmax,
                             int32_t tmax, double *W, void *stream) {
+  const Range range_("mcg_wilson_loops");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, U, "U"))) return st;
@@ -1494,6 +1514,7 @@ mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, cons
 mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int32_t n,
                                   const mcg_gauge *Gstar, int32_t ckpt_every, mcg_field *gradU, double *loss,
                                   double *dRho, double *dEps, void *stream) {
+  const Range range_("mcg_smear_mcg_backward");
   if (!ctx) return MCG_EINVAL;
   mcg_status st;
   if ((st = check_field(ctx, U, "U")) || (st = check_field(ctx, gradU, "gradU")) ||
