@@ -334,6 +334,19 @@ mcg_status mcg_get_option(mcg_ctx *ctx, int32_t option, int32_t *value);
  * pi/3 - |arg(t e^{-2 pi i m/3})|. */
 mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G,
                               int8_t *Z, double *min_margin, void *stream);
+/* mcg_center_project for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * Z and *min_margin, bit for bit, but no call allocates anything.  The
+ * per-block minima live in a static 512 KiB scratch array of the library,
+ * one per GPU (held until the process ends), so lattices of at most 2^25
+ * sites are accepted (larger: MCG_EINVAL; use mcg_center_project).
+ * min_margin NULL: nothing is copied back and the stream is not
+ * synchronised, so the call can be captured into a graph.  MCG_OPT_CHECK is
+ * not applied (the check would need scratch).  All calls on one GPU share
+ * that array and keep the last call's contents: calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race. */
+mcg_status mcg_center_project_noalloc(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G,
+                                      int8_t *Z, double *min_margin, void *stream);
 /* P-vortex plaquettes of Z: n = (m_mu(x) + m_nu(x+mu) - m_mu(x+nu) - m_nu(x)) mod 3
  * for mu < nu; counts of n != 0 in total, per plane (0,1),(0,2),(0,3),(1,2),
  * (1,3),(2,3), and per charge n = 1, 2 (host outputs; per_plane/per_charge

@@ -83,6 +83,8 @@ SIGNATURES = {
                            C.POINTER(FixOpts), C.POINTER(FixResult), _P]),
     "mcg_center_project": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P,
                                 C.POINTER(C.c_double), _P]),
+    "mcg_center_project_noalloc": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P,
+                                        C.POINTER(C.c_double), _P]),
     "mcg_count_vortices": (_S, [_CTX, _P, Dims, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int64), _P]),
     "mcg_unitarity": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), C.POINTER(C.c_double),

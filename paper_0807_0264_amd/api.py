@@ -333,6 +333,22 @@ def center_project(U, G=None):
     return Z, mm.value
 
 
+def center_project_noalloc(U, G=None, Z=None, want_margin=True):
+    """center_project through the allocation-free entry point (lattices of up to 2^25 sites): Z
+    (int8 [4, V], allocated here unless given) and the minimum margin, or None when want_margin is
+    False (then the stream is not synchronised)."""
+    if Z is None:
+        Z = torch.empty((4, volume(U.L)), dtype=torch.int8, device=U.data.device)
+    ctx = context(U.data.device.index)
+    f = U.abi()
+    g = G.abi() if G is not None else None
+    mm = C.c_double()
+    _check(A.load().mcg_center_project_noalloc(ctx, C.byref(f), C.byref(g) if g is not None else None,
+                                               C.c_void_p(Z.data_ptr()), C.byref(mm) if want_margin else None,
+                                               _stream()), ctx)
+    return Z, (mm.value if want_margin else None)
+
+
 def count_vortices(Z, L):
     ctx = context(Z.device.index)
     tot = C.c_int64()

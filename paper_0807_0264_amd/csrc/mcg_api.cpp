@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -50,7 +51,40 @@ struct mcg_ctx {
   size_t scratch_used = 0;
   int stop_every = 1;  // stop test only after sweeps numbered by multiples of this (MCG_OPT_STOP_EVERY)
   int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
+  double *noalloc = nullptr;  // this device's address of the allocation-free entry point's scratch
+  std::string noalloc_err;    // why it is missing, if it is
 };
+
+// Scratch of the allocation-free centre projection (mcg_center_project_noalloc): the per-block
+// minima of the centre-phase margin, one per 256 half sites, then the final minimum.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in: the kernels get this device's address of it, looked up once per device.
+constexpr int NOALLOC_PARTS = 65536;  // ceil(V / 512) <= 65536: lattices of up to 2^25 sites
+static __device__ __align__(256) double scratch[NOALLOC_PARTS + 32];
+
+namespace {
+
+std::mutex noalloc_mu;
+std::vector<double *> noalloc_ptr;  // per device, filled on the first context of that device
+
+// With `device` current: this device's address of `scratch` (cached), or the runtime's error.
+hipError_t noalloc_scratch(int device, double **out) {
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if ((int)noalloc_ptr.size() <= device) noalloc_ptr.resize(device + 1, nullptr);
+  if (!noalloc_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e;
+    }
+    noalloc_ptr[device] = (double *)p;
+  }
+  *out = noalloc_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -659,6 +693,9 @@ mcg_status mcg_create(mcg_ctx **out, int32_t device) {
   if (hipSetDevice(device) != hipSuccess) return MCG_EHIP;
   mcg_ctx *ctx = new mcg_ctx();
   ctx->device = device;
+  // the allocation-free entry point's scratch on this device; without it only that call fails
+  const hipError_t e = noalloc_scratch(device, &ctx->noalloc);
+  if (e != hipSuccess) ctx->noalloc_err = hipGetErrorString(e);
   *out = ctx;
   return MCG_OK;
 }
@@ -1303,6 +1340,37 @@ mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge 
     HIPCHK(launch_center_project<double>(g, U->ptr, gp, Z, (double *)ctx->part.p, dmin, s));
   else
     HIPCHK(launch_center_project<float>(g, U->ptr, gp, Z, (double *)ctx->part.p, dmin, s));
+  if (min_margin) {
+    HIPCHK(hipMemcpyAsync(min_margin, dmin, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return MCG_OK;
+}
+
+mcg_status mcg_center_project_noalloc(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, int8_t *Z,
+                                      double *min_margin, void *stream) {
+  const Range range_("mcg_center_project_noalloc");
+  if (!ctx) return MCG_EINVAL;
+  mcg_status st;
+  if ((st = check_field(ctx, U, "U"))) return st;
+  if (G && (st = check_gauge(ctx, G, U->d, "G"))) return st;
+  if (!Z) return fail(ctx, MCG_EINVAL, "Z is NULL");
+  const Geom g = geom_of(U->d);
+  const int nb = field_blocks256(g);
+  if (nb > NOALLOC_PARTS)
+    return fail(ctx, MCG_EINVAL,
+                "mcg_center_project_noalloc: %d sites exceed its limit of %d (2^25); use mcg_center_project",
+                g.V, 512 * NOALLOC_PARTS);
+  if (!ctx->noalloc)
+    return fail(ctx, MCG_EHIP, "mcg_center_project_noalloc: no device address of its scratch: %s",
+                ctx->noalloc_err.c_str());
+  hipStream_t s = (hipStream_t)stream;
+  const double *gp = G ? G->ptr : nullptr;
+  double *part = ctx->noalloc, *dmin = ctx->noalloc + NOALLOC_PARTS;
+  if (U->prec == MCG_F64)
+    HIPCHK(launch_center_project<double>(g, U->ptr, gp, Z, part, dmin, s));
+  else
+    HIPCHK(launch_center_project<float>(g, U->ptr, gp, Z, part, dmin, s));
   if (min_margin) {
     HIPCHK(hipMemcpyAsync(min_margin, dmin, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

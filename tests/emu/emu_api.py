@@ -205,6 +205,16 @@ def center_project(U, G=None):
     return Z, mm.value
 
 
+def center_project_noalloc(U, G=None, want_margin=True):
+    Z = np.zeros((4, V(U.L)), np.int8)
+    f = U.abi()
+    g = G.abi() if G is not None else None
+    mm = C.c_double()
+    check(lib().mcg_center_project_noalloc(ctx(), C.byref(f), C.byref(g) if g is not None else None, ptr(Z),
+                                           C.byref(mm) if want_margin else None, None))
+    return Z, (mm.value if want_margin else None)
+
+
 def count_vortices(Z, L):
     tot = C.c_int64()
     pp = (C.c_int64 * 6)()

@@ -27,6 +27,8 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 #define __shared__ static thread_local_block_shared
 
 using std::atan2;
@@ -213,6 +215,11 @@ inline hipError_t hipGetDeviceCount(int *n) {
   return hipSuccess;
 }
 inline hipError_t hipSetDevice(int) { return hipSuccess; }
+// a __device__ variable is a host variable here: its address is the symbol's
+inline hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+  *p = const_cast<void *>(symbol);
+  return hipSuccess;
+}
 inline hipError_t hipDeviceSynchronize() { return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipMalloc(void **p, size_t n) {

@@ -101,6 +101,12 @@ def scenario_project(L, prec):
     G = E.host_gauge(Gf)
     Zd, mmin = E.center_project(E.links(U, prec), Gf)
     Z = E.z_interchange(Zd, L)
+    # the allocation-free entry point: the same integers and margin from the library's static scratch
+    Zn, mn = E.center_project_noalloc(E.links(U, prec), Gf)
+    check(np.array_equal(Zn, Zd) and mn == mmin, "allocation-free projection")
+    Zn2, none = E.center_project_noalloc(E.links(U, prec), None, want_margin=False)
+    check(none is None and np.array_equal(Zn2, E.center_project(E.links(U, prec), None)[0]),
+          "allocation-free projection without G or margin")
     Zo, margin = O.center_project(U, G)
     safe = margin > 1e-4
     check(np.array_equal(Z[safe], Zo[safe]), "centre integers")
