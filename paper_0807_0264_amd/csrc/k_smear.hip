@@ -13,7 +13,7 @@ template <typename T>
 hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
                              hipStream_t s) {
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
-  dim3 grid((g.Vh + 127) / 128, 8);
+  const int grid = 8 * ((g.Vh + 127) / 128);
   if (eps == 1.0)
     k_smear<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (V2<T> *)out, (T)rho, (T)wp, (T)wr);
   else
