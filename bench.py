@@ -44,6 +44,9 @@ BYTES_PER_SITE_UPDATE = {(True, True): 8 * 48 * 2 + 48, (True, False): 8 * 48 * 
 # g needed once: 48 B per site), writes the 8 links and its own g (8 * 48 * 2 + 48 + 48); per
 # site-update the mean of the two
 BYTES_PER_SITE_UPDATE_PAIRED = (8 * 48 + 48 + 8 * 48 * 2 + 48 + 48) // 2
+# the model of a site-update with full 3x3 FP32 links and an FP64 G read and written in every
+# half-sweep: 8 * 72 * 2 + 2 * 144 B
+SURVEY_BYTES_PER_SITE_UPDATE = 8 * 72 * 2 + 2 * 144
 # the fold kernel's bytes per site-update it folds, with 25 sweeps per fold (raw sweeps, and
 # fixes re-unitarising every 50): g read once (48 B) + G(x) read and written once per 25
 FOLD_BYTES_PER_SITE_UPDATE = {True: 48 + 2 * 96 / 25, False: 48 + 2 * 144 / 25}
@@ -75,18 +78,23 @@ def make_inputs(api, synth, torch):
 
 
 def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6, max_sweeps=5000,
-                  r_match=1e-6):
+                  r_match=1e-6, deep_tol=1e-10):
     """Gribov copies of one field: Haar-random start transforms g_c, each copy
     fixed without smearing and with nsmear stout steps (then carried back and
     re-fixed), centre-projected and vortex-counted.  Every level runs once with
     all copies batched in FP32 links and once copy by copy with FP64 links
-    (the same FP32-rounded input); a copy counts as matched when its two final
-    R agree to r_match; both paths stop on the same criterion dR < tol = 1e-6.
-    Rounding differences steer a copy to a different
-    local maximum after enough over-relaxed sweeps, so the R distributions of
-    the two precisions are compared too (means, standard errors, Welch t), and
-    the sweep at which each copy's two R trajectories first differ by more
-    than r_match is reported."""
+    (the same FP32-rounded input); both stop on the same criterion
+    dR < tol = 1e-6.  "Equal final R" is read three ways:
+    (a) the same stop test, R distributions compared (rounding steers a copy
+        to a different local maximum after enough over-relaxed sweeps, so the
+        two paths' copies are different maxima: means, standard errors, Welch
+        t, and the sweep at which each copy's two R trajectories first differ
+        by more than r_match);
+    (b) every batched FP32 copy polished by a batched FP64 fix from its own G
+        to the same dR < tol, timed as part of the FP32 path: a copy counts
+        when its FP32 R lies within r_match of the polished FP64 R;
+    (c) both paths' copies polished in FP64 to dR < deep_tol (untimed): a copy
+        counts when its R lies within r_match of the maximum it converges to."""
     import numpy as np
 
     L = U.L
@@ -106,6 +114,12 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
                             traj=first["traj"][:first["sweeps"] + 1]))
         return out
 
+    def polish(G, ptol):
+        """batched FP64 fix of every copy from its own transform to dR < ptol: final R and sweeps"""
+        _, inf = api.fix_batch([U64] * ncopies, [g.clone() for g in G],
+                               **dict(fix_kw, tol=ptol, max_sweeps=20000))
+        return [x["R"] for x in inf], [x["sweeps"] for x in inf]
+
     def batched(n):
         G = [g.clone() for g in G0]
         infos_s = None
@@ -114,7 +128,15 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
             G, infos_s = api.fix_batch([S] * ncopies, G, want_traj=True, **fix_kw)
             del S
         G, infos = api.fix_batch([U] * ncopies, G, want_traj=True, **fix_kw)
-        return finish(U, G, infos, infos_s)
+        out = finish(U, G, infos, infos_s)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        Rp, sw = polish(G, tol)  # (b): part of the FP32 path
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        for x, r, k, g in zip(out, Rp, sw, G):
+            x.update(R_polished=r, polish_sweeps=k, polish_s=dt, G=g)
+        return out
 
     def plain(n):
         S = api.smear(U64, rho, 1.0, n) if n else None
@@ -127,7 +149,10 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
             g, i = api.fix(U64, g, want_traj=True, **fix_kw)
             G.append(g)
             infos.append(i)
-        return finish(U64, G, infos, infos_s)
+        out = finish(U64, G, infos, infos_s)
+        for x, g in zip(out, G):
+            x["G"] = g
+        return out
 
     def mean_sem(x):
         x = np.asarray(x, dtype=float)
@@ -140,6 +165,7 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
 
     best64, _ = api.autotune(U64)
     best32, _ = api.autotune_batch([U] * ncopies)  # the batch the FP32 path fixes
+    sched32 = api.tune_batch([U] * ncopies)
     levels = []
     for n in (0, nsmear):
         runs = {}
@@ -151,17 +177,34 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
             runs[name + "_s"] = time.time() - t0
             log(f"gribov copies n={n} {name}: {runs[name + '_s']:.2f} s")
         a, b = runs["fp32_batched"], runs["fp64_plain"]
+        # (c): both paths' copies polished to deep_tol, untimed
+        t0 = time.time()
+        deep32, dsw32 = polish([x.pop("G") for x in a], deep_tol)
+        deep64, dsw64 = polish([y.pop("G") for y in b], deep_tol)
+        log(f"gribov copies n={n}: FP64 polish of both paths to dR < {deep_tol}: {time.time() - t0:.2f} s")
         dR = [abs(x["R"] - y["R"]) for x, y in zip(a, b)]
         matched = [c for c in range(ncopies) if dR[c] <= r_match]
+        pol = [abs(x["R"] - x["R_polished"]) for x in a]
+        own32 = [abs(x["R"] - r) for x, r in zip(a, deep32)]
+        own64 = [abs(y["R"] - r) for y, r in zip(b, deep64)]
         (ma, sa), (mb, sb) = mean_sem([x["R"] for x in a]), mean_sem([x["R"] for x in b])
         (va, vsa), (vb, vsb) = mean_sem([x["vf"] for x in a]), mean_sem([x["vf"] for x in b])
         div = [diverge(x["traj"], y["traj"]) for x, y in zip(a, b)]
+        t_polish = a[0]["polish_s"]
         levels.append(dict(
             smear=f"stout rho={rho} n={n}" if n else "none",
             copies_per_s_fp32_batched=round(ncopies / runs["fp32_batched_s"], 3),
             copies_per_s_fp64_plain=round(ncopies / runs["fp64_plain_s"], 3),
             speedup=round(runs["fp64_plain_s"] / runs["fp32_batched_s"], 3),
-            matched_copies=len(matched), max_abs_dR_matched=max([dR[c] for c in matched], default=None),
+            fp32_polish_s=round(t_polish, 3), fp32_polish_sweeps=[x["polish_sweeps"] for x in a],
+            speedup_without_polish=round(runs["fp64_plain_s"] / (runs["fp32_batched_s"] - t_polish), 3),
+            matched_copies_polished=sum(d <= r_match for d in pol), max_abs_dR_polished=max(pol),
+            matched_copies_converged_fp32=sum(d <= r_match for d in own32),
+            matched_copies_converged_fp64=sum(d <= r_match for d in own64),
+            max_abs_dR_converged_fp32=max(own32), max_abs_dR_converged_fp64=max(own64),
+            deep_polish_sweeps_fp32=dsw32, deep_polish_sweeps_fp64=dsw64,
+            matched_copies_same_copy=len(matched),
+            max_abs_dR_matched=max([dR[c] for c in matched], default=None),
             R_mean_sem_fp32=[round(ma, 7), round(sa, 7)], R_mean_sem_fp64=[round(mb, 7), round(sb, 7)],
             R_welch_t=round((ma - mb) / np.hypot(sa, sb), 3),
             vortex_fraction_mean_sem_fp32=[round(va, 6), round(vsa, 6)],
@@ -173,8 +216,16 @@ def gribov_copies(api, synth, torch, U, ncopies=16, rho=0.1, nsmear=20, tol=1e-6
             vortex_fraction_fp64=[round(x["vf"], 5) for x in b],
             not_converged=sum(x["status"] != 0 for x in a + b)))
     return dict(workload=f"{ncopies} Haar Gribov copies of one {'x'.join(map(str, L))} field, "
-                         f"tol {tol}, all copies batched (FP32 links) vs one by one (FP64 links)",
-                fp64_variant=best64, fp32_variant=best32, levels=levels)
+                         f"tol {tol}, all copies batched (FP32 links, then a batched FP64 polish to the "
+                         f"same tol, timed) vs one by one (FP64 links)",
+                readings=dict(polished="FP32 R within r_match of the FP64 polish of the same copy (timed)",
+                              converged=f"R within r_match of the copy's maximum (FP64 polish to dR < "
+                                        f"{deep_tol}, untimed), for each path",
+                              same_copy="FP32 and FP64 final R of one copy within r_match",
+                              r_match=r_match),
+                fp64_variant=best64, fp32_variant=best32,
+                fp32_schedule={k: (round(v, 4) if isinstance(v, float) else v) for k, v in sched32.items()},
+                levels=levels)
 
 
 # Wilson loops of the static-potential measurement (Sec. III.B) on the 20^3x40
@@ -342,6 +393,13 @@ def roofline(api, torch, U, nsweeps=200, runs=5):
                                / HBM_PEAK_GBS, 4),
                     note="context only: the same time per site-update against the bytes a plain half-sweep "
                          "with the ring needs (each link written in both half-sweeps)")} if paired else {}),
+                survey_model=dict(
+                    bytes_per_site_update=SURVEY_BYTES_PER_SITE_UPDATE,
+                    GBps=round(site_updates * SURVEY_BYTES_PER_SITE_UPDATE / (ms * 1e-3) / 1e9, 1),
+                    frac=round(site_updates * SURVEY_BYTES_PER_SITE_UPDATE / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    note="effective rate: the same time per site-update against the bytes of the plain "
+                         "full-matrix form (8 FP32 links read and written, FP64 G read and written); "
+                         "above 1 because the two-row form, the ring and paired sweeps move fewer bytes"),
                 sweep_loop=dict(ms_per_half_sweep=round(loop_ms, 4), bytes_per_site_update=loop_bps,
                                 GBps=round(site_updates * loop_bps / (loop_ms * 1e-3) / 1e9, 1),
                                 note="api.sweeps end to end (conversions of W and G to and from the "
@@ -389,7 +447,7 @@ def cpu_baseline(U64, target_s=15.0):
                 single_thread_value=round(n1 * (V // 2) / dt1, 1))
 
 
-def profile_run(api, torch, synth):
+def profile_run(api, torch, synth, variant=None):
     """Fixed work for rocprofv3: plain device copies of known size (to
     calibrate the byte counters), 25 warm-up sweeps, then 20 measured sweeps
     (the last 40 half-sweep launches and the last fold) at 32^3x64 FP32 in the
@@ -400,7 +458,11 @@ def profile_run(api, torch, synth):
     U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(5, 0), 5.7, 50), 1)
     others = [api.to_links(synth.haar_links_gpu(Lb, synth.sub_seed(5, 10 + i)), 1)
               for i, Lb in enumerate(LATTICES[1:])]
-    best, _ = api.autotune_batch([U] + others)
+    if variant is None:
+        best, _ = api.autotune_batch([U] + others)
+    else:
+        api.set_variant(1, variant)
+        best = variant
     del others
     nbytes = 1 << 30
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -429,6 +491,9 @@ def main():
     ap.add_argument("--profile-backward", action="store_true", help="one backward pass at 16^4 for rocprofv3")
     ap.add_argument("--profile-roofline", action="store_true",
                     help="the roofline measurement alone (batch-tuned variant), for rocprofv3")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="with --profile / --profile-roofline: this half-sweep variant instead of the tuned one "
+                         "(so that separate counter runs time the same instantiations)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the workload is one MI355X's share of the job, and "
@@ -440,7 +505,7 @@ def main():
     from paper_0807_0264_amd import api, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.profile:
-        profile_run(api, torch, synth)
+        profile_run(api, torch, synth, args.variant)
         return
     if args.profile_step:
         fields = make_inputs(api, synth, torch)
@@ -459,7 +524,11 @@ def main():
         U = api.to_links(synth.heatbath_field_gpu(L, synth.sub_seed(5, 0), 5.7, 50), 1)
         others = [api.to_links(synth.haar_links_gpu(Lb, synth.sub_seed(5, 10 + i)), 1)
                   for i, Lb in enumerate(LATTICES[1:])]
-        best, _ = api.autotune_batch([U] + others)
+        if args.variant is None:
+            best, _ = api.autotune_batch([U] + others)
+        else:
+            api.set_variant(1, args.variant)
+            best = args.variant
         del others
         print(json.dumps(dict(profile="done", variant=best, roofline=roofline(api, torch, U))))
         return
@@ -474,9 +543,13 @@ def main():
         return
 
     fields = make_inputs(api, synth, torch)
-    # tuned on the batch the step fixes: every timed launch covers all four fields
+    # tuned on the batch the step fixes: every timed launch covers all four fields; first the
+    # variant alone (kept as the context's variant: the raw sweeps of the roofline use it), then
+    # variant and schedule together (kept for the batch's shape: the step's fixes use it)
     best, ms = api.autotune_batch([U for _, U, _ in fields])
     log(f"autotuned half-sweep variant {best}: ms per batched half-sweep {[round(x, 3) for x in ms]}")
+    sched = api.tune_batch([U for _, U, _ in fields])
+    log(f"tuned sweep schedule of the batch: {sched}")
 
     for w in range(args.warmup):
         t0 = time.time()
@@ -522,13 +595,16 @@ def main():
                                      "batched MCG fix to dR<1e-7 (omega=1.7), carried-back batched "
                                      "re-fix, centre projection, vortex count",
                             links="fp32", gauge="fp64", reductions="fp64", half_sweep_variant=best,
+                            tuned_schedule=dict(sched, ms_per_sweep=round(sched["ms_per_sweep"], 4),
+                                                ms_default=round(sched["ms_default"], 4)),
                             sweep_order={0: "forward", 1: "odd half-sweeps in reverse tile order",
                                          2: "odd half-sweeps in reverse tile order; each XCD a "
-                                            "contiguous range of every field's tiles"}[api.get_sweep_order()],
+                                            "contiguous range of every field's tiles"}[sched["order"]],
                             transform="per-half-sweep g in a ring, folded into G every 25 sweeps"
                             if api.get_defer_g() else "G updated in every half-sweep",
-                            sweeps="paired: the even half-sweep leaves the links to the odd one"
-                            if api.get_defer_g() and api.get_paired() else "plain half-sweeps",
+                            sweeps=("paired: the even half-sweep leaves the links to the odd one"
+                                    if api.get_defer_g() and sched["paired"] else "plain half-sweeps")
+                            + (f", {sched['slabs']} slabs per half-sweep" if sched["slabs"] > 1 else ""),
                             per_field=[dict(L=x["L"], sweeps_smeared=x["sweeps_smeared"], sweeps=x["sweeps"],
                                             R_smeared=round(x["R_smeared"], 7), R=round(x["R"], 7),
                                             vortex_fraction=round(x["vortex_fraction"], 5))

@@ -229,6 +229,37 @@ mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant,
  * form.  Uses the scratch that mcg_fix_batch on the same fields uses. */
 mcg_status mcg_autotune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, int32_t *best_variant,
                               double *ms_per_halfsweep, void *stream);
+/* The launch variant and the schedule of the fixing sweeps, tuned on a batch.
+ * mcg_tune_batch times whole sweeps (both half-sweeps over all B fields, as
+ * mcg_fix_batch runs them: working copies of U with G = 1 in the context's
+ * storage form, with its transform ring or FP64 handoff slot) in three
+ * stages: every variant under the schedule fixes of this batch would use
+ * now; every schedule -- tile order (MCG_OPT_ORDER 0/1/2) x paired sweeps
+ * (MCG_OPT_PAIRED: 0/1 for FP32 with the ring, 0/2 for FP64 in the two-row
+ * form, else 0) x slabs (MCG_OPT_SLABS 1/2/4) -- under the best variant;
+ * every variant under the best schedule.  Each stage runs three interleaved
+ * passes of 4 timed sweeps per point (after one untimed) and ranks points by
+ * their median.  The choice is kept in the context for this batch shape
+ * (precision, storage form, transform ring, update variant and the fields'
+ * extents in order) and used by mcg_fix and mcg_fix_batch on batches of that
+ * shape instead of the context's variant and schedule options, until
+ * mcg_set_variant, mcg_set_option(MCG_OPT_ORDER / _PAIRED / _SLABS) or
+ * mcg_clear_tuning.  All schedules give the same bits: they change only the
+ * order in which independent sites are visited and where a site's g waits.
+ * Not available with MCG_OPT_HITS > 1 or MCG_OPT_EXACT (one fixed variant).
+ * best (nullable, host): the choice, its median ms per sweep, and that of
+ * the schedule the batch had before (ms_default). */
+typedef struct {
+  int32_t variant;     /* half-sweep variant, as in mcg_set_variant */
+  int32_t order;       /* MCG_OPT_ORDER value */
+  int32_t paired;      /* MCG_OPT_PAIRED value */
+  int32_t slabs;       /* MCG_OPT_SLABS value */
+  double ms_per_sweep; /* median over the three passes, one sweep over the batch */
+  double ms_default;   /* the same for the variant and schedule in use before tuning */
+} mcg_tune_choice;
+mcg_status mcg_tune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_tune_choice *best,
+                          void *stream);
+mcg_status mcg_clear_tuning(mcg_ctx *ctx);
 mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant);
 mcg_status mcg_get_variant(mcg_ctx *ctx, int32_t prec, int32_t *variant);
 

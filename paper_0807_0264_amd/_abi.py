@@ -37,6 +37,11 @@ class Gauge(C.Structure):
     _fields_ = [("d", Dims), ("ptr", C.c_void_p)]
 
 
+class TuneChoice(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("order", C.c_int32), ("paired", C.c_int32), ("slabs", C.c_int32),
+                ("ms_per_sweep", C.c_double), ("ms_default", C.c_double)]
+
+
 class FixOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("omega", C.c_double), ("max_sweeps", C.c_int32),
                 ("reunit_every", C.c_int32), ("start_sweep", C.c_int32),
@@ -99,6 +104,8 @@ SIGNATURES = {
     "mcg_autotune": (_S, [_CTX, C.POINTER(Field), C.POINTER(C.c_int32), C.POINTER(C.c_double), _P]),
     "mcg_autotune_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                 _P]),
+    "mcg_tune_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(TuneChoice), _P]),
+    "mcg_clear_tuning": (_S, [_CTX]),
     "mcg_set_variant": (_S, [_CTX, C.c_int32, C.c_int32]),
     "mcg_get_variant": (_S, [_CTX, C.c_int32, C.POINTER(C.c_int32)]),
     "mcg_set_option": (_S, [_CTX, C.c_int32, C.c_int32]),

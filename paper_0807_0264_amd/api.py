@@ -425,6 +425,23 @@ def autotune_batch(Us):
     return best.value, list(ms)
 
 
+def tune_batch(Us):
+    """Tune the half-sweep variant and the sweep schedule (tile order, paired sweeps, slabs) on the
+    batch Us, as fix_batch runs it; the choice is kept for batches of this shape.  Returns it as a
+    dict (variant, order, paired, slabs, ms_per_sweep, ms_default)."""
+    ctx = context(Us[0].data.device.index)
+    B = len(Us)
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    c = A.TuneChoice()
+    _check(A.load().mcg_tune_batch(ctx, B, F, C.byref(c), _stream()), ctx)
+    return {k: getattr(c, k) for k, _ in A.TuneChoice._fields_}
+
+
+def clear_tuning(device=None):
+    ctx = context(device)
+    _check(A.load().mcg_clear_tuning(ctx), ctx)
+
+
 def set_variant(prec, variant, device=None):
     ctx = context(device)
     _check(A.load().mcg_set_variant(ctx, _prec_of(prec), int(variant)), ctx)

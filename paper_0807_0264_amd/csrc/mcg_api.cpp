@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -51,6 +52,9 @@ struct mcg_ctx {
   size_t scratch_used = 0;
   int stop_every = 1;  // stop test only after sweeps numbered by multiples of this (MCG_OPT_STOP_EVERY)
   int variant[2][2] = {{2, 2}, {2, 2}};  // half-sweep variant per [precision][two-row form]
+  // launch variant and schedule chosen by mcg_tune_batch, per batch shape (tune_key); used by the
+  // fixes of that shape until an explicit variant or schedule option is set
+  std::map<std::string, mcg_tune_choice> tuned;
   double *noalloc = nullptr;  // this device's address of the allocation-free entry point's scratch
   std::string noalloc_err;    // why it is missing, if it is
 };
@@ -297,6 +301,30 @@ template <typename T> int plan_slabs(LatDesc<T> *D, int B, int n, int bs, int gr
 // the tile-order argument of a half-sweep of parity par: bit 0 reverse, bit 1 contiguous XCD ranges
 static int tile_order(int order, int par) { return order == 0 ? 0 : (order == 2 ? 2 : 0) | (par == 1 ? 1 : 0); }
 
+// The launch variant and schedule of the fixing sweeps of a batch: what mcg_tune_batch chose for
+// this batch shape (precision, storage form, transform ring, update variant, the fields' extents in
+// order), else the context's variant and options.  Re-linearisation hits and exact steps run with
+// 256-thread blocks (variant 2).  Every choice gives the same bits.
+struct Sched {
+  int variant, order, paired, nslab;
+};
+std::string tune_key(const mcg_ctx *ctx, int B, const mcg_field *U) {
+  std::string k = std::to_string(U[0].prec) + (ctx->c12 ? "/rows" : "/full") + (ctx->defer_g ? "/ring" : "/G") +
+                  "/hits" + std::to_string(ctx->hits) + (ctx->exact ? "/exact" : "");
+  for (int b = 0; b < B; b++) {
+    k += ":";
+    for (int j = 0; j < 4; j++) k += (j ? "x" : "") + std::to_string(U[b].d.L[j]);
+  }
+  return k;
+}
+Sched schedule_of(const mcg_ctx *ctx, int B, const mcg_field *U) {
+  Sched r{ctx->variant[U[0].prec][ctx->c12], ctx->order, ctx->paired, ctx->nslab};
+  const auto it = ctx->tuned.find(tune_key(ctx, B, U));
+  if (it != ctx->tuned.end()) r = Sched{it->second.variant, it->second.order, it->second.paired, it->second.slabs};
+  if (ctx->hits > 1 || ctx->exact) r.variant = 2;
+  return r;
+}
+
 template <typename T> struct FixRun {
   mcg_ctx *ctx;
   hipStream_t s;
@@ -408,8 +436,8 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
     if ((st = check_inputs(ctx, &U[b], &G[b], s))) return st;
   }
   const bool c12 = ctx->c12;
-  // re-linearisation hits run in one instantiation with 256-thread blocks (variant 2)
-  const int variant = (ctx->hits > 1 || ctx->exact) ? 2 : ctx->variant[prec][c12], bs = variant_block(variant);
+  const Sched sc = schedule_of(ctx, B, U);
+  const int variant = sc.variant, bs = variant_block(variant);
   if ((int)ctx->W.size() < B) {
     ctx->W.resize(B);
     ctx->G12.resize(B);
@@ -458,16 +486,16 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   // the ring (or FP64's handoff slot for paired sweeps) last, after everything the fix cannot do
   // without
   if (ring) ring = reserve_rings(ctx, B, U, gring_sweeps(re));
-  bool hand = prec == MCG_F64 && c12 && ctx->paired == 2;
+  bool hand = prec == MCG_F64 && c12 && sc.paired == 2;
   if (hand) hand = reserve_rings(ctx, B, U, 1);
   for (int b = 0; b < B && (ring || hand); b++) hD[b].gring = (V2<T> *)ctx->gring[b].p;
   FixRun<T> run{ctx, s, B, variant, bs, total, c12, ctx->desc.p, omega};
-  run.nslab = plan_slabs(hD, B, ctx->nslab, bs, run.grid);
+  run.nslab = plan_slabs(hD, B, sc.nslab, bs, run.grid);
   run.hits = ctx->hits;
   run.exact = ctx->exact ? 1 : 0;
-  run.order = ctx->order;
+  run.order = sc.order;
   run.C = ring ? gring_sweeps(re) : 0;
-  run.paired = ctx->paired != 0;
+  run.paired = sc.paired != 0;
   run.hand = hand;
   HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->states.p, hS, sizeof(FixState) * B, hipMemcpyHostToDevice, s));
@@ -1135,6 +1163,158 @@ static mcg_status autotune_impl(mcg_ctx *ctx, int B, const mcg_field *U, int32_t
   return MCG_OK;
 }
 
+// Launch variant and schedule of the fixing sweeps, tuned on the batch itself: whole sweeps (both
+// half-sweeps) over all B fields, on working copies of U with G = 1, in the context's storage form
+// and with the transform ring (one sweep's slots) or FP64 handoff slot that fixes would use.  The
+// search runs in three stages -- every variant under the context's current schedule, every
+// schedule (tile order x paired sweeps x slabs) under the best variant, every variant under the
+// best schedule -- each stage in three interleaved passes, points ranked by their median.  The
+// schedule changes only the order in which independent sites are visited and where g waits, so
+// every point gives the same bits.
+template <typename T>
+static mcg_status tune_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_tune_choice *out, hipStream_t s) {
+  const bool c12 = ctx->c12;
+  const int prec = U[0].prec;
+  if (ctx->hits > 1 || ctx->exact)
+    return fail(ctx, MCG_EINVAL, "mcg_tune_batch: re-linearisation hits and exact steps run one fixed variant");
+  bool ring = prec == MCG_F32 && ctx->defer_g;
+  mcg_status st;
+  if ((int)ctx->W.size() < B) {
+    ctx->W.resize(B);
+    ctx->G12.resize(B);
+    ctx->fpart.resize(B);
+    ctx->traj.resize(B);
+    ctx->gring.resize(B);
+  }
+  if ((st = ensure(ctx, ctx->desc, sizeof(LatDesc<T>) * B)) || (st = ensure_pinned(ctx, sizeof(LatDesc<T>) * B)))
+    return st;
+  size_t gfull = 0;
+  for (int b = 0; b < B; b++) {
+    if ((st = ensure(ctx, ctx->W[b], work_field_bytes(U[b].d, prec, c12))) ||
+        (st = ensure(ctx, ctx->G12[b], gauge_form_bytes(U[b].d, c12))))
+      return st;
+    gfull = std::max(gfull, mcg_gauge_bytes(U[b].d));
+  }
+  if (c12 && (st = ensure(ctx, ctx->grad_a, gfull))) return st;
+  if (ring) ring = reserve_rings(ctx, B, U, 1);
+  // FP64 paired sweeps need the handoff slot; without it (memory) they are not tried
+  bool hand = prec == MCG_F64 && c12;
+  if (hand) hand = reserve_rings(ctx, B, U, 1);
+  for (int b = 0; b < B; b++) {
+    const Geom g = geom_of(U[b].d);
+    if (c12) {
+      HIPCHK(launch_gauge_identity(g, (double *)ctx->grad_a.p, s));
+      HIPCHK(launch_gauge_form(g, (const double *)ctx->grad_a.p, (double *)ctx->G12[b].p, true, s));
+      HIPCHK(launch_links_form<T>(g, U[b].ptr, ctx->W[b].p, true, s));
+    } else {
+      HIPCHK(launch_gauge_identity(g, (double *)ctx->G12[b].p, s));
+      HIPCHK(hipMemcpyAsync(ctx->W[b].p, U[b].ptr, field_bytes(U[b].d, prec), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  LatDesc<T> *hD = (LatDesc<T> *)ctx->h_pinned;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // one point: WARM sweeps, then REPS timed sweeps; ms per sweep
+  constexpr int WARM = 1, REPS = 4;
+  auto time_point = [&](const Sched &p, double &ms) -> mcg_status {
+    const int bs = variant_block(p.variant);
+    int total = 0;
+    for (int b = 0; b < B; b++) {
+      LatDesc<T> d;
+      memset(&d, 0, sizeof d);
+      d.g = geom_of(U[b].d);
+      d.blk0 = total;
+      d.nblk = nblocks(d.g, bs);
+      d.nslab = 1;
+      d.W = (V2<T> *)ctx->W[b].p;
+      d.G = (double2 *)ctx->G12[b].p;
+      d.gring = (ring || hand) ? (V2<T> *)ctx->gring[b].p : nullptr;
+      hD[b] = d;
+      total += d.nblk;
+    }
+    FixRun<T> run{ctx, s, B, p.variant, bs, total, c12, ctx->desc.p, 1.7};
+    run.gated = false;
+    run.stateful = false;
+    run.order = p.order;
+    run.C = ring ? 1 : 0;  // g to ring slots 0 and 1; no fold is timed
+    run.paired = p.paired != 0;
+    run.hand = hand && p.paired == 2;
+    run.nslab = plan_slabs(hD, B, p.nslab, bs, run.grid);
+    HIPCHK(hipMemcpyAsync(ctx->desc.p, hD, sizeof(LatDesc<T>) * B, hipMemcpyHostToDevice, s));
+    mcg_status q = MCG_OK;
+    for (int k = 0; k < WARM + REPS && q == MCG_OK; k++) {
+      if (k == WARM) HIPCHK(hipEventRecord(e0, s));
+      q = run.halfsweeps(false);
+      run.since_fold = 0;
+    }
+    if (q) return q;
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));  // also frees the pinned staging area for the next point
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    ms = (double)t / REPS;
+    return MCG_OK;
+  };
+  auto stage = [&](std::vector<Sched> &pts, std::vector<double> &med) -> mcg_status {
+    std::vector<double> t(3 * pts.size());
+    for (int pass = 0; pass < 3; pass++)
+      for (size_t i = 0; i < pts.size(); i++) {
+        const mcg_status q = time_point(pts[i], t[3 * i + pass]);
+        if (q) return q;
+      }
+    med.resize(pts.size());
+    for (size_t i = 0; i < pts.size(); i++) {
+      const double a = t[3 * i], b = t[3 * i + 1], c = t[3 * i + 2];
+      med[i] = std::max(std::min(a, b), std::min(std::max(a, b), c));
+    }
+    return MCG_OK;
+  };
+  auto argmin = [](const std::vector<double> &v) { return (int)(std::min_element(v.begin(), v.end()) - v.begin()); };
+  // the paired values fixes of this precision and form can run
+  std::vector<int> pairings{0};
+  if (c12 && ring) pairings.push_back(1);
+  if (c12 && hand) pairings.push_back(2);
+  // the schedule fixes of this batch would run now (for FP32, paired value 2 means paired too)
+  Sched base = schedule_of(ctx, B, U);
+  if (prec == MCG_F32 && base.paired == 2) base.paired = 1;
+  if (std::find(pairings.begin(), pairings.end(), base.paired) == pairings.end()) base.paired = 0;
+  std::vector<Sched> pts;
+  std::vector<double> med;
+  mcg_status rc = MCG_OK;
+  for (int v = 0; v < NUM_VARIANTS; v++) pts.push_back(Sched{v, base.order, base.paired, base.nslab});
+  if (!(rc = stage(pts, med))) {
+    const double t_cur = med[base.variant];
+    const int v1 = argmin(med);
+    pts.clear();
+    for (int o = 0; o <= 2; o++)
+      for (int pr : pairings)
+        for (int n : {1, 2, 4}) pts.push_back(Sched{v1, o, pr, n});
+    if (!(rc = stage(pts, med))) {
+      const Sched sb = pts[argmin(med)];
+      pts.clear();
+      for (int v = 0; v < NUM_VARIANTS; v++) pts.push_back(Sched{v, sb.order, sb.paired, sb.nslab});
+      if (!(rc = stage(pts, med))) {
+        const int i = argmin(med);
+        mcg_tune_choice c;
+        memset(&c, 0, sizeof c);
+        c.variant = pts[i].variant;
+        c.order = pts[i].order;
+        c.paired = pts[i].paired;
+        c.slabs = pts[i].nslab;
+        c.ms_per_sweep = med[i];
+        c.ms_default = t_cur;
+        ctx->tuned[tune_key(ctx, B, U)] = c;
+        if (out) *out = c;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 extern "C" {
 
 mcg_status mcg_autotune(mcg_ctx *ctx, const mcg_field *U, int32_t *best_variant, double *ms_per_halfsweep,
@@ -1158,8 +1338,28 @@ mcg_status mcg_autotune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, int32
              : autotune_impl<float>(ctx, B, U, best_variant, ms_per_halfsweep, (hipStream_t)stream);
 }
 
+mcg_status mcg_tune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_tune_choice *best, void *stream) {
+  const Range range_("mcg_tune_batch");
+  if (!ctx) return MCG_EINVAL;
+  if (B < 1 || !U) return fail(ctx, MCG_EINVAL, "empty batch");
+  mcg_status st;
+  for (int b = 0; b < B; b++) {
+    if ((st = check_field(ctx, &U[b], "U"))) return st;
+    if (U[b].prec != U[0].prec) return fail(ctx, MCG_EINVAL, "field %d: precision differs within the batch", b);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  return U[0].prec == MCG_F64 ? tune_impl<double>(ctx, B, U, best, s) : tune_impl<float>(ctx, B, U, best, s);
+}
+
+mcg_status mcg_clear_tuning(mcg_ctx *ctx) {
+  if (!ctx) return MCG_EINVAL;
+  ctx->tuned.clear();
+  return MCG_OK;
+}
+
 mcg_status mcg_set_variant(mcg_ctx *ctx, int32_t prec, int32_t variant) {
   if (!ctx) return MCG_EINVAL;
+  ctx->tuned.clear();  // an explicit variant overrides what was tuned
   if ((prec != MCG_F64 && prec != MCG_F32) || variant < 0 || variant >= NUM_VARIANTS)
     return fail(ctx, MCG_EINVAL, "bad precision or variant");
   ctx->variant[prec][ctx->c12] = variant;
@@ -1182,6 +1382,7 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
   }
   if (option == MCG_OPT_SLABS) {
     if (value < 1 || value > MAX_SLABS) return fail(ctx, MCG_EINVAL, "MCG_OPT_SLABS takes 1..%d", MAX_SLABS);
+    ctx->tuned.clear();  // an explicit schedule overrides what was tuned
     ctx->nslab = value;
     return MCG_OK;
   }
@@ -1192,6 +1393,7 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
   }
   if (option == MCG_OPT_ORDER) {
     if (value < 0 || value > 2) return fail(ctx, MCG_EINVAL, "MCG_OPT_ORDER takes 0, 1 or 2");
+    ctx->tuned.clear();  // an explicit schedule overrides what was tuned
     ctx->order = value;
     return MCG_OK;
   }
@@ -1202,6 +1404,7 @@ mcg_status mcg_set_option(mcg_ctx *ctx, int32_t option, int32_t value) {
   }
   if (option == MCG_OPT_PAIRED) {
     if (value < 0 || value > 2) return fail(ctx, MCG_EINVAL, "MCG_OPT_PAIRED takes 0, 1 or 2");
+    ctx->tuned.clear();  // an explicit schedule overrides what was tuned
     ctx->paired = value;
     return MCG_OK;
   }

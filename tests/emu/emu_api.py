@@ -287,6 +287,18 @@ def autotune_batch(Us):
     return best.value, list(ms)
 
 
+def tune_batch(Us):
+    B = len(Us)
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    c = A.TuneChoice()
+    check(lib().mcg_tune_batch(ctx(), B, F, C.byref(c), None))
+    return {k: getattr(c, k) for k, _ in A.TuneChoice._fields_}
+
+
+def clear_tuning():
+    check(lib().mcg_clear_tuning(ctx()))
+
+
 def set_update_variant(hits, stop_every, exact=False):
     check(lib().mcg_set_option(ctx(), 3, hits))
     check(lib().mcg_set_option(ctx(), 4, stop_every))

@@ -140,6 +140,19 @@ def scenario_batch(prec):
     check(0 <= best < 6 and all(t > 0 for t in ms) and E.get_variant(prec) == best, f"autotune_batch {best}")
     check(all(np.array_equal(a, E.host_links(W)) for a, W in zip(before, Ws)), "autotune leaves U alone")
     E.set_variant(prec, 2)
+    # the schedule tuner: its choice is kept for this batch shape and gives the bits of the defaults
+    Gref = [E.gauge(G) for G in G0s]
+    ref = E.fix_batch([E.links(U, prec) for U in Us], Gref, tols, maxs, reunit_every=3, check_every=2)
+    c = E.tune_batch(Ws)
+    check(0 <= c["variant"] < 6 and 0 <= c["order"] <= 2 and c["paired"] in ((0, 1) if prec else (0, 2))
+          and c["slabs"] in (1, 2, 4) and c["ms_per_sweep"] > 0 and c["ms_default"] > 0, f"tune_batch {c}")
+    check(all(np.array_equal(a, E.host_links(W)) for a, W in zip(before, Ws)), "tune_batch leaves U alone")
+    Gt = [E.gauge(G) for G in G0s]
+    got = E.fix_batch([E.links(U, prec) for U in Us], Gt, tols, maxs, reunit_every=3, check_every=2)
+    check(all(np.array_equal(a["traj"], b["traj"]) and a["R"] == b["R"] for a, b in zip(ref, got)) and
+          all(np.array_equal(E.host_gauge(a), E.host_gauge(b)) for a, b in zip(Gref, Gt)),
+          f"tuned schedule gives the default bits ({c})")
+    E.clear_tuning()
 
 
 def scenario_planted():

@@ -310,6 +310,30 @@ def test_autotune_batch(S, g, api):
         api.set_variant(1, 2)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_tune_batch(S, g, api, prec):
+    """The schedule tuner (variant x tile order x paired sweeps x slabs, timed as whole sweeps over
+    the batch) keeps its choice for the batch shape; the fix of that batch afterwards, in the tuned
+    schedule, gives the bits of the untuned fix (every schedule visits independent sites in another
+    order, nothing else), G and trajectory, across a re-unitarisation and a graph replay."""
+    Ls = [(6, 6, 6, 10), (4, 4, 4, 4), (8, 8, 8, 16)]
+    Us = [g.rounded(field(S, L, 1036 + i), prec) for i, L in enumerate(Ls)]
+    kw = dict(tol=-1.0, max_sweeps=12, reunit_every=5, want_traj=True)
+    try:
+        Ga, a = api.fix_batch([g.links(U, prec) for U in Us], None, **kw)
+        c = api.tune_batch([g.links(U, prec) for U in Us])
+        print(f"prec {prec}: tuned {c}")
+        assert 0 <= c["variant"] < 6 and 0 <= c["order"] <= 2 and c["slabs"] in (1, 2, 4)
+        assert c["paired"] in ((0, 1) if prec == 1 else (0, 2))
+        assert c["ms_per_sweep"] > 0 and c["ms_default"] > 0
+        Gb, b = api.fix_batch([g.links(U, prec) for U in Us], None, **kw)
+        for x, y, ga, gb in zip(a, b, Ga, Gb):
+            assert np.array_equal(x["traj"], y["traj"])
+            assert np.array_equal(g.host_gauge(ga), g.host_gauge(gb))
+    finally:
+        api.clear_tuning()
+
+
 def test_synth_gpu_is_bitwise_cpu(S, g):
     for L, n in (((4, 4, 4, 4), 4), ((6, 4, 4, 8), 3)):
         a = S.heatbath_field(L, S.sub_seed(1040), 5.7, n)
