@@ -77,18 +77,21 @@ __global__ __launch_bounds__(256) void k_loss_seed(Geom g, const V2<T> *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// The adjoint kernels map blockIdx.x through xcd_range within each grid row (one row per
-// direction and parity), so a site's neighbours mostly share an XCD's L2; per-block partial sums
-// are stored by tile, so their summation order does not depend on the mapping.
+// The adjoint kernels run one block per (tile, direction, parity): the eight blocks of a tile follow
+// each other and each XCD takes a contiguous range of tiles (xcd_range), so a site's neighbours
+// mostly share an XCD's L2 and the links of a tile are loaded while still cached; per-block partial
+// sums are stored by (direction and parity, tile), so their summation order does not depend on the
+// mapping.
 // --------------------------------------------------------------- pass A
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gOut, V2<T> *__restrict__ gU,
                                                     V2<T> *__restrict__ gC, T rho, T wp, T wr, double *part,
                                                     int *flag) {
-  const int tile = xcd_range((int)blockIdx.x, (int)gridDim.x);
+  const int w = xcd_range((int)blockIdx.x, (int)gridDim.x), nT = (int)gridDim.x >> 3;
+  const int tile = w >> 3, row = w & 7;
   const int h = tile * 128 + threadIdx.x;
-  const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
+  const int mu = row >> 1, par = row & 1;
   double drho = 0.0, deps = 0.0;
   if (h < g.Vh) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
   const double a = block_sum<128>(drho);
   const double b = block_sum<128>(deps);
   if (threadIdx.x == 0) {
-    const int blk = blockIdx.y * gridDim.x + tile;
+    const int blk = row * nT + tile;
     part[2 * blk] = a;
     part[2 * blk + 1] = b;
   }
@@ -170,9 +173,10 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
 template <typename T>
 __global__ __launch_bounds__(128) void k_eps_rect(Geom g, const V2<T> *__restrict__ U,
                                                   const V2<T> *__restrict__ gC, T rho, double *part) {
-  const int tile = xcd_range((int)blockIdx.x, (int)gridDim.x);
+  const int w = xcd_range((int)blockIdx.x, (int)gridDim.x), nT = (int)gridDim.x >> 3;
+  const int tile = w >> 3, row = w & 7;
   const int h = tile * 128 + threadIdx.x;
-  const int mu = blockIdx.y >> 1, par = blockIdx.y & 1;
+  const int mu = row >> 1, par = row & 1;
   double deps = 0.0;
   if (h < g.Vh) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(128) void k_eps_rect(Geom g, const V2<T> *__restric
     deps = (double)rdot(gc, scale(rho * T(1.0 / 12.0), Cr));
   }
   const double b = block_sum<128>(deps);
-  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + tile] = b;
+  if (threadIdx.x == 0) part[row * nT + tile] = b;
 }
 
 // --------------------------------------------------------------- pass B
@@ -310,9 +314,10 @@ __device__ __forceinline__ void path_terms(const Geom &g, const Links<T> &L, con
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
-  const int h = xcd_range((int)blockIdx.x, (int)gridDim.x) * 128 + threadIdx.x;
+  const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
+  const int h = (w >> 3) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
-  const int lnu = blockIdx.y >> 1, par = blockIdx.y & 1;
+  const int lnu = (w & 7) >> 1, par = w & 1;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh}, GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};
   int y[4];
   coords_of(g, par, h, y);

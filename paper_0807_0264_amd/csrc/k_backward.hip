@@ -19,8 +19,8 @@ template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, double rho,
                                double eps, double *part, int *flag, hipStream_t s) {
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
-  dim3 grid((g.Vh + 127) / 128, 8);
-  const int nb = (int)(grid.x * grid.y);
+  const int grid = 8 * ((g.Vh + 127) / 128);
+  const int nb = grid;
   if (eps == 1.0) {
     k_step_adj_a<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gOut, (V2<T> *)gU,
                                                 (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);

@@ -119,12 +119,16 @@ template <typename T> __device__ __forceinline__ M3<T> exp_su3(const M3<T> &A) {
 // Plaquette part Cp and rectangle part Cr (OI only) of the staple sum of
 // link (c, mu): paths from x to x+mu.  Per nu != mu and per sign of nu: the
 // plaquette staple and the rectangles 2x1 ahead, 2x1 behind (long in mu) and
-// 1x2 (long in nu).
+// 1x2 (long in nu).  Rectangles that end on the same link share the last
+// product: the 2x1-behind and 1x2 paths of one nu and sign both end on the
+// link into x+mu along nu, and every 2x1-ahead path ends on U_mu(x+mu)^dag, so
+// their prefixes are summed first and multiplied by that link once.
 template <typename T, bool OI>
 __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const int c[4], int mu,
                                         M3<T> &Cp, M3<T> &Cr) {
   Cp = m_zero<T>();
   Cr = m_zero<T>();
+  M3<T> ahead = m_zero<T>();  // OI: sum of the 2x1-ahead prefixes, closed by U_mu(x+mu)^dag at the end
   int cpm[4], cmm[4];
   moved(g, c, mu, +1, cpm);
   moved(g, c, mu, -1, cmm);
@@ -154,39 +158,35 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
       moved(g, cmm, nu, -1, cmmmn);
       moved(g, cmn, nu, -1, cm2n);
       moved(g, cm2n, mu, +1, cm2npm);
-      const M3<T> umu_xpm = L.at(g, cpm, mu);  // U_mu(x+mu)
       const M3<T> umu_xmm = L.at(g, cmm, mu);  // U_mu(x-mu)
-      M3<T> t;
-      // +nu, 2x1 ahead: U_nu(x) U_mu(x+nu) U_mu(x+nu+mu) U_nu(x+2mu)^dag U_mu(x+mu)^dag
+      M3<T> t, end;
+      // +nu, 2x1 ahead: U_nu(x) U_mu(x+nu) U_mu(x+nu+mu) U_nu(x+2mu)^dag [U_mu(x+mu)^dag]
       t = mul(up, L.at(g, cpnpm, mu));
-      t = mul_nd(t, L.at(g, cp2m, nu));
-      add_to(mul_nd(t, umu_xpm), Cr);
-      // +nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) U_nu(x+mu)^dag
+      add_to(mul_nd(t, L.at(g, cp2m, nu)), ahead);
+      // +nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) [U_nu(x+mu)^dag]
       t = mul_dn(umu_xmm, L.at(g, cmm, nu));
       t = mul(t, L.at(g, cmmpn, mu));
-      t = mul(t, umu_xpn);
-      add_to(mul_nd(t, unu_xpm), Cr);
-      // +nu, 1x2: U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag U_nu(x+mu)^dag
+      end = mul(t, umu_xpn);
+      // +nu, 1x2: U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag [U_nu(x+mu)^dag]
       t = mul(unu_x, L.at(g, cpn, nu));
       t = mul(t, L.at(g, cp2n, mu));
-      t = mul_nd(t, L.at(g, cpnpm, nu));
-      add_to(mul_nd(t, unu_xpm), Cr);
-      // -nu, 2x1 ahead: U_nu(x-nu)^dag U_mu(x-nu) U_mu(x-nu+mu) U_nu(x-nu+2mu) U_mu(x+mu)^dag
+      add_to(mul_nd(t, L.at(g, cpnpm, nu)), end);
+      add_to(mul_nd(end, unu_xpm), Cr);
+      // -nu, 2x1 ahead: U_nu(x-nu)^dag U_mu(x-nu) U_mu(x-nu+mu) U_nu(x-nu+2mu) [U_mu(x+mu)^dag]
       t = mul(dn, L.at(g, cmnpm, mu));
-      t = mul(t, L.at(g, cmnp2m, nu));
-      add_to(mul_nd(t, umu_xpm), Cr);
-      // -nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_mu(x-nu) U_nu(x-nu+mu)
+      add_to(mul(t, L.at(g, cmnp2m, nu)), ahead);
+      // -nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_mu(x-nu) [U_nu(x-nu+mu)]
       t = dag(mul(L.at(g, cmmmn, nu), umu_xmm));
       t = mul(t, L.at(g, cmmmn, mu));
-      t = mul(t, umu_xmn);
-      add_to(mul(t, unu_xmnpm), Cr);
-      // -nu, 1x2: U_nu(x-nu)^dag U_nu(x-2nu)^dag U_mu(x-2nu) U_nu(x-2nu+mu) U_nu(x-nu+mu)
+      end = mul(t, umu_xmn);
+      // -nu, 1x2: U_nu(x-nu)^dag U_nu(x-2nu)^dag U_mu(x-2nu) U_nu(x-2nu+mu) [U_nu(x-nu+mu)]
       t = dag(mul(L.at(g, cm2n, nu), unu_xmn));
       t = mul(t, L.at(g, cm2n, mu));
-      t = mul(t, L.at(g, cm2npm, nu));
-      add_to(mul(t, unu_xmnpm), Cr);
+      add_to(mul(t, L.at(g, cm2npm, nu)), end);
+      add_to(mul(end, unu_xmnpm), Cr);
     }
   }
+  if (OI) add_to(mul_nd(ahead, L.at(g, cpm, mu)), Cr);  // ... U_mu(x+mu)^dag
 }
 
 }  // namespace mcg
