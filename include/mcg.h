@@ -210,6 +210,32 @@ mcg_status mcg_fix(mcg_ctx *ctx, const mcg_field *U, mcg_gauge *G, const mcg_fix
 mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge *G,
                          const mcg_fix_opts *opts, mcg_fix_result *res, void *stream);
 
+/* The whole preconditioned path of Sec. II.B for a batch of B fields (one
+ * precision; Gribov copies and/or lattices of unequal sizes): n smearing steps
+ * of every field (rho, eps as in mcg_smear; the smeared fields live in
+ * context scratch), one mcg_fix_batch of the smeared fields from G, one of
+ * the original fields from the transforms that gave, then the centre
+ * projection of every fixed field (Z[b]: caller-owned device array [4][V] as
+ * in mcg_center_project) and its P-vortex count.  G[b]: the start transform
+ * on entry (mcg_gauge_identity for plain fixing), the total on exit.  opts as
+ * in mcg_fix_batch, used by both fixes.  res (host, B entries): both fixes'
+ * results, the minimum centre-phase margin and the counts of mcg_count_vortices.
+ * Each field's results equal, bit for bit, those of the same calls made one by
+ * one; the host synchronises once per block of sweeps of each fix (stop flags)
+ * and once at the end.  Returns MCG_WNOTCONV if either fix of any field ran
+ * out of sweeps. */
+typedef struct {
+  mcg_fix_result smeared;  /* fix of the smeared field ("smeared maximum" of Table I) */
+  mcg_fix_result fixed;    /* fix of the original field from the smeared field's transform */
+  double min_margin;       /* as mcg_center_project */
+  int64_t vortices;        /* P-vortex plaquettes, as mcg_count_vortices */
+  int64_t per_plane[6];
+  int64_t per_charge[2];
+} mcg_precond_result;
+mcg_status mcg_precondition_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, double rho, double eps,
+                                  int32_t n, const mcg_fix_opts *opts, mcg_gauge *G, int8_t *const *Z,
+                                  mcg_precond_result *res, void *stream);
+
 /* ---- kernel variants and autotuning ------------------------------------------------ */
 /* The half-sweep kernel has MCG_NUM_VARIANTS variants: variant v uses blocks
  * of {64, 128, 256}[v % 3] threads and targets 1 + v / 3 waves per SIMD.

@@ -54,6 +54,11 @@ class FixResult(C.Structure):
                 ("pad_", C.c_int32)]
 
 
+class PrecondResult(C.Structure):
+    _fields_ = [("smeared", FixResult), ("fixed", FixResult), ("min_margin", C.c_double),
+                ("vortices", C.c_int64), ("per_plane", C.c_int64 * 6), ("per_charge", C.c_int64 * 2)]
+
+
 _P = C.c_void_p
 _S = C.c_int32  # mcg_status
 _CTX = C.c_void_p
@@ -86,6 +91,9 @@ SIGNATURES = {
                      C.POINTER(FixResult), _P]),
     "mcg_fix_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.POINTER(Gauge),
                            C.POINTER(FixOpts), C.POINTER(FixResult), _P]),
+    "mcg_precondition_batch": (_S, [_CTX, C.c_int32, C.POINTER(Field), C.c_double, C.c_double, C.c_int32,
+                                    C.POINTER(FixOpts), C.POINTER(Gauge), C.POINTER(C.c_void_p),
+                                    C.POINTER(PrecondResult), _P]),
     "mcg_center_project": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P,
                                 C.POINTER(C.c_double), _P]),
     "mcg_center_project_noalloc": (_S, [_CTX, C.POINTER(Field), C.POINTER(Gauge), _P,

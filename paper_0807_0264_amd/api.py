@@ -320,6 +320,29 @@ def fix_batch(Us, Gs=None, tol=1e-7, max_sweeps=5000, omega=1.7, reunit_every=50
     return Gs, [_result(R[b], trajs[b]) for b in range(B)]
 
 
+def precondition_batch(Us, rho=0.1, eps=1.0, n=10, Gs=None, tol=1e-7, max_sweeps=5000, omega=1.7,
+                       reunit_every=50, check_every=50):
+    """The whole preconditioned path (Sec. II.B) for a batch of fields in one library call: smear,
+    fix the smeared fields, fix the originals from their transforms, project and count.  Gs: start
+    transforms (identity if None), updated in place to the totals.  Returns (Gs, Zs, results), each
+    result a dict with the two fixes' results, the minimum margin and the vortex counts."""
+    B = len(Us)
+    Gs = Gs if Gs is not None else [gauge_identity(U.L, U.data.device.index) for U in Us]
+    Zs = [torch.empty((4, volume(U.L)), dtype=torch.int8, device=U.data.device) for U in Us]
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    GG = (A.Gauge * B)(*[G.abi() for G in Gs])
+    O = (A.FixOpts * B)(*[_opts(tol, max_sweeps, omega, reunit_every, 0, check_every, None) for _ in range(B)])
+    Zp = (C.c_void_p * B)(*[Z.data_ptr() for Z in Zs])
+    R = (A.PrecondResult * B)()
+    ctx = context(Us[0].data.device.index)
+    _check(A.load().mcg_precondition_batch(ctx, B, F, float(rho), float(eps), int(n), O, GG, Zp, R, _stream()),
+           ctx, allow_warn=True)
+    out = [dict(smeared=_result(r.smeared, None), fixed=_result(r.fixed, None), min_margin=r.min_margin,
+                vortices=dict(total=r.vortices, per_plane=list(r.per_plane), per_charge=list(r.per_charge)))
+           for r in R]
+    return Gs, Zs, out
+
+
 def center_project(U, G=None):
     """Centre integers Z (int8 tensor [4, V], lexicographic sites) of U^G and the
     minimum centre-phase margin (Sec. II.A)."""

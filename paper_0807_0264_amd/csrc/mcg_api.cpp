@@ -38,6 +38,8 @@ struct mcg_ctx {
   DevBuf part, scalars, counts, states, desc, tmpfield, grad_a, grad_b, gC, ckpt, bw_part, w12, g12;
   DevBuf line_a, line_b, wl_part, wl_res, wl_img;  // Wilson loops: line fields, partial sums, results, images
   std::vector<DevBuf> W, G12, fpart, traj, gring;
+  std::vector<DevBuf> smeared;  // mcg_precondition_batch: the smeared fields
+  DevBuf pc_part, pc_counts;    // mcg_precondition_batch: margin partials and vortex counters
   void *h_pinned = nullptr;
   size_t h_pinned_cap = 0;
   bool c12 = true;  // fixing keeps W and G as two rows (MCG_OPT_TWO_ROW)
@@ -610,6 +612,79 @@ mcg_status fix_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_gauge *G, const
   return worst;
 }
 
+// ------------------------------------------------------- the whole path of a batch
+// Sec. II.B for B fields at once: smear every field (n steps), fix the smeared fields together
+// from G (batched, graph-captured blocks), fix the original fields together from the smeared
+// fields' transforms, then project every fixed field onto Z3 and count its P-vortices.  The
+// projections and counts of all fields are queued together and read back with one
+// synchronisation; the fixes synchronise once per block of sweeps to read their stop flags.
+template <typename T>
+static mcg_status precondition_impl(mcg_ctx *ctx, int B, const mcg_field *U, double rho, double eps, int n,
+                                    const mcg_fix_opts *opts, mcg_gauge *G, int8_t *const *Z,
+                                    mcg_precond_result *res, hipStream_t s) {
+  mcg_status st;
+  size_t maxbytes = 0;
+  for (int b = 0; b < B; b++) maxbytes = std::max(maxbytes, field_bytes(U[b].d, U[b].prec));
+  if ((int)ctx->smeared.size() < B) ctx->smeared.resize(B);
+  std::vector<mcg_field> S(U, U + B);
+  if (n > 0) {
+    for (int b = 0; b < B; b++) {
+      if ((st = ensure(ctx, ctx->smeared[b], field_bytes(U[b].d, U[b].prec)))) return st;
+      S[b].ptr = ctx->smeared[b].p;
+    }
+    if (n > 1 && (st = ensure(ctx, ctx->tmpfield, maxbytes))) return st;
+    for (int b = 0; b < B; b++) {
+      const Geom g = geom_of(U[b].d);
+      const void *src = U[b].ptr;
+      for (int k = 0; k < n; k++) {  // ping-pong so that the last step writes S[b]
+        void *dst = ((n - 1 - k) % 2 == 0) ? S[b].ptr : ctx->tmpfield.p;
+        HIPCHK(launch_smear_step<T>(g, src, dst, rho, eps, s));
+        src = dst;
+      }
+    }
+  }
+  std::vector<mcg_fix_result> rs(B), rf(B);
+  const mcg_status s1 = fix_impl<T>(ctx, B, S.data(), G, opts, rs.data(), s, true);
+  if (s1 < 0) return s1;
+  const mcg_status s2 = fix_impl<T>(ctx, B, U, G, opts, rf.data(), s, true);
+  if (s2 < 0) return s2;
+  // every field's projection and count, then one copy back
+  std::vector<size_t> p0(B + 1, 0);
+  for (int b = 0; b < B; b++) p0[b + 1] = p0[b] + (size_t)field_blocks256(geom_of(U[b].d));
+  if ((st = ensure(ctx, ctx->pc_part, sizeof(double) * (p0[B] + B))) ||
+      (st = ensure(ctx, ctx->pc_counts, sizeof(unsigned long long) * 12 * B)) ||
+      (st = ensure_pinned(ctx, sizeof(double) * B + sizeof(unsigned long long) * 12 * B)))
+    return st;
+  double *part = (double *)ctx->pc_part.p, *mins = part + p0[B];
+  unsigned long long *counts = (unsigned long long *)ctx->pc_counts.p;
+  HIPCHK(launch_zero((double *)counts, 12 * B, s));  // a fill kernel, not a memset: graph-safe
+  for (int b = 0; b < B; b++) {
+    const Geom g = geom_of(U[b].d);
+    HIPCHK(launch_center_project<T>(g, U[b].ptr, G[b].ptr, Z[b], part + p0[b], mins + b, s));
+    HIPCHK(launch_count_vortices(g, Z[b], counts + 12 * b, s));
+  }
+  double *hmin = (double *)ctx->h_pinned;
+  unsigned long long *hcnt = (unsigned long long *)(hmin + B);
+  HIPCHK(hipMemcpyAsync(hmin, mins, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hcnt, counts, sizeof(unsigned long long) * 12 * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < B; b++) {
+    mcg_precond_result &r = res[b];
+    memset(&r, 0, sizeof r);
+    r.smeared = rs[b];
+    r.fixed = rf[b];
+    r.min_margin = hmin[b];
+    const unsigned long long *c = hcnt + 12 * b;
+    for (int p = 0; p < 6; p++) {
+      r.per_plane[p] = (int64_t)(c[2 * p] + c[2 * p + 1]);
+      r.per_charge[0] += (int64_t)c[2 * p];
+      r.per_charge[1] += (int64_t)c[2 * p + 1];
+      r.vortices += r.per_plane[p];
+    }
+  }
+  return s1 == MCG_WNOTCONV || s2 == MCG_WNOTCONV ? MCG_WNOTCONV : MCG_OK;
+}
+
 // ----------------------------------------------------------------- backward
 // L = R(S_n(U)^G*): forward with a checkpoint every c steps, seed grad_S_n,
 // then per segment (last first) recompute the c fields from the checkpoint
@@ -737,7 +812,9 @@ mcg_status mcg_destroy(mcg_ctx *ctx) {
                     &ctx->line_a, &ctx->line_b, &ctx->wl_part, &ctx->wl_res, &ctx->wl_img};
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
-  for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj, &ctx->gring})
+  for (DevBuf *b : {&ctx->pc_part, &ctx->pc_counts})
+    if (b->p) (void)hipFree(b->p);
+  for (auto *v : {&ctx->W, &ctx->G12, &ctx->fpart, &ctx->traj, &ctx->gring, &ctx->smeared})
     for (DevBuf &b : *v)
       if (b.p) (void)hipFree(b.p);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
@@ -1521,6 +1598,26 @@ mcg_status mcg_fix_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_gauge 
   hipStream_t s = (hipStream_t)stream;
   return U[0].prec == MCG_F64 ? fix_impl<double>(ctx, B, U, G, opts, res, s, true)
                               : fix_impl<float>(ctx, B, U, G, opts, res, s, true);
+}
+
+mcg_status mcg_precondition_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, double rho, double eps,
+                                  int32_t n, const mcg_fix_opts *opts, mcg_gauge *G, int8_t *const *Z,
+                                  mcg_precond_result *res, void *stream) {
+  const Range range_("mcg_precondition_batch");
+  if (!ctx) return MCG_EINVAL;
+  if (!U || B < 1) return fail(ctx, MCG_EINVAL, "empty batch");
+  if (!G || !opts || !Z || !res) return fail(ctx, MCG_EINVAL, "NULL argument");
+  if (n < 0 || std::isnan(rho) || std::isnan(eps)) return fail(ctx, MCG_EINVAL, "bad smearing parameters");
+  mcg_status st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int b = 0; b < B; b++) {
+    if ((st = check_field(ctx, &U[b], "U"))) return st;
+    if (U[b].prec != U[0].prec) return fail(ctx, MCG_EINVAL, "field %d: precision differs within the batch", b);
+    if (!Z[b]) return fail(ctx, MCG_EINVAL, "Z[%d] is NULL", b);
+    if ((st = check_inputs(ctx, &U[b], nullptr, s))) return st;
+  }
+  return U[0].prec == MCG_F64 ? precondition_impl<double>(ctx, B, U, rho, eps, n, opts, G, Z, res, s)
+                              : precondition_impl<float>(ctx, B, U, rho, eps, n, opts, G, Z, res, s);
 }
 
 mcg_status mcg_center_project(mcg_ctx *ctx, const mcg_field *U, const mcg_gauge *G, int8_t *Z,

@@ -287,6 +287,19 @@ def autotune_batch(Us):
     return best.value, list(ms)
 
 
+def precondition_batch(Us, Gs, rho, eps, n, tol, max_sweeps, reunit_every=50, check_every=10):
+    B = len(Us)
+    Zs = [np.zeros((4, V(U.L)), np.int8) for U in Us]
+    F = (A.Field * B)(*[U.abi() for U in Us])
+    GG = (A.Gauge * B)(*[G.abi() for G in Gs])
+    O = (A.FixOpts * B)(*[_opts(tol, max_sweeps, 1.7, reunit_every, 0, check_every, None) for _ in range(B)])
+    Zp = (C.c_void_p * B)(*[Z.ctypes.data for Z in Zs])
+    R = (A.PrecondResult * B)()
+    check(lib().mcg_precondition_batch(ctx(), B, F, rho, eps, n, O, GG, Zp, R, None), allow_warn=True)
+    return Zs, [dict(Rs=r.smeared.R, ss=r.smeared.sweeps, R=r.fixed.R, s=r.fixed.sweeps, m=r.min_margin,
+                     v=r.vortices) for r in R]
+
+
 def tune_batch(Us):
     B = len(Us)
     F = (A.Field * B)(*[U.abi() for U in Us])

@@ -153,6 +153,21 @@ def scenario_batch(prec):
           all(np.array_equal(E.host_gauge(a), E.host_gauge(b)) for a, b in zip(Gref, Gt)),
           f"tuned schedule gives the default bits ({c})")
     E.clear_tuning()
+    # the whole path of the batch in one call: the bits of its calls made one by one
+    for rho, eps, n in ((0.1, 1.0, 2), (0.06, -0.25, 1)):
+        Gp = [E.gauge(G) for G in G0s]
+        Zs, rp = E.precondition_batch([E.links(U, prec) for U in Us], Gp, rho, eps, n, 1e-12, 6, reunit_every=3,
+                                      check_every=2)
+        Sm = [E.smear(E.links(U, prec), rho, eps, n) for U in Us]
+        Gq = [E.gauge(G) for G in G0s]
+        i1 = E.fix_batch(Sm, Gq, [1e-12] * 3, [6] * 3, reunit_every=3, check_every=2)
+        i2 = E.fix_batch([E.links(U, prec) for U in Us], Gq, [1e-12] * 3, [6] * 3, reunit_every=3, check_every=2)
+        for b in range(3):
+            Zq, mq = E.center_project(E.links(Us[b], prec), Gq[b])
+            check(rp[b]["Rs"] == i1[b]["R"] and rp[b]["R"] == i2[b]["R"] and rp[b]["s"] == i2[b]["sweeps"] and
+                  np.array_equal(E.host_gauge(Gp[b]), E.host_gauge(Gq[b])) and np.array_equal(Zs[b], Zq) and
+                  rp[b]["m"] == mq and rp[b]["v"] == E.count_vortices(Zq, Ls[b])["total"],
+                  f"precondition_batch field {b} ({rho}, {eps}, {n})")
 
 
 def scenario_planted():

@@ -334,6 +334,28 @@ def test_tune_batch(S, g, api, prec):
         api.clear_tuning()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("rho,eps,n", [(0.1, 1.0, 4), (0.06, -0.25, 3), (0.1, 1.0, 0)])
+def test_precondition_batch_equals_its_calls(S, g, api, prec, rho, eps, n):
+    """The whole path of a batch in one library call gives, field by field, the bits of the calls it
+    is made of: smear, fix_batch of the smeared fields, fix_batch of the originals from their
+    transforms, centre projection and vortex count."""
+    Ls = [(6, 6, 6, 10), (4, 4, 4, 4), (8, 4, 4, 8)]
+    Us = [g.links(g.rounded(field(S, L, 1050 + i), prec), prec) for i, L in enumerate(Ls)]
+    kw = dict(tol=1e-9 if prec == 0 else 1e-6, max_sweeps=400, omega=1.7, reunit_every=50, check_every=50)
+    Gs, Zs, res = api.precondition_batch(Us, rho, eps, n, **kw)
+    Sm = [api.smear(U, rho, eps, n) for U in Us]
+    G1, i1 = api.fix_batch(Sm, None, **kw)
+    G2, i2 = api.fix_batch(Us, G1, **kw)
+    for b, L in enumerate(Ls):
+        assert res[b]["smeared"]["R"] == i1[b]["R"] and res[b]["smeared"]["sweeps"] == i1[b]["sweeps"]
+        assert res[b]["fixed"]["R"] == i2[b]["R"] and res[b]["fixed"]["sweeps"] == i2[b]["sweeps"]
+        assert np.array_equal(g.host_gauge(Gs[b]), g.host_gauge(G2[b]))
+        Z, m = api.center_project(Us[b], G2[b])
+        assert np.array_equal(Zs[b].cpu().numpy(), Z.cpu().numpy()) and res[b]["min_margin"] == m
+        assert res[b]["vortices"] == api.count_vortices(Z, L)
+
+
 def test_synth_gpu_is_bitwise_cpu(S, g):
     for L, n in (((4, 4, 4, 4), 4), ((6, 4, 4, 8), 3)):
         a = S.heatbath_field(L, S.sub_seed(1040), 5.7, n)
