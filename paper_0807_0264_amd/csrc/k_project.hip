@@ -6,6 +6,8 @@
 //   A plaquette is a P-vortex when (m_mu(x) + m_nu(x+mu) - m_mu(x+nu) - m_nu(x))
 //   mod 3 is non-zero.
 
+#include <algorithm>
+
 #include "project_kernels.hpp"
 
 namespace mcg {
@@ -21,7 +23,9 @@ hipError_t launch_center_project(const Geom &g, const void *U, const double *G, 
 
 hipError_t launch_count_vortices(const Geom &g, const int8_t *Z, unsigned long long *counts,
                                  hipStream_t s) {
-  k_count_vortices<<<(g.V + 255) / 256, 256, 0, s>>>(g, Z, counts);
+  // a few blocks per CU, each site visited by one thread of a grid-stride loop
+  const int blocks = std::min((g.V + 255) / 256, 2048);
+  k_count_vortices<<<blocks, 256, 0, s>>>(g, Z, counts);
   return hipGetLastError();
 }
 
