@@ -236,8 +236,8 @@ __device__ __forceinline__ void take_factor(M3<T> &pre, M3<T> &post, const M3<T>
 }
 
 // Walk path W from pos, step K onwards, collecting the factors of every step but J.
-template <typename T, int W, int J, int K>
-__device__ __forceinline__ void walk_path(const Geom &g, const Links<T> &L, int pos[4], int mu, int nu, int sg,
+template <typename T, int W, int J, int K, class LD>
+__device__ __forceinline__ void walk_path(const Geom &g, const LD &L, int pos[4], int mu, int nu, int sg,
                                           M3<T> &pre, M3<T> &post) {
   if constexpr (K < Path<W>::n) {
     constexpr int sym = Path<W>::sym[K], sgn = Path<W>::sgn[K];
@@ -252,14 +252,14 @@ __device__ __forceinline__ void walk_path(const Geom &g, const Links<T> &L, int 
     }
 #pragma unroll
     for (int q = 0; q < 4; q++) pos[q] = t[q];
-    walk_path<T, W, J, K + 1>(g, L, pos, mu, nu, sg, pre, post);
+    walk_path<T, W, J, K + 1, LD>(g, L, pos, mu, nu, sg, pre, post);
   }
 }
 
 // Add to acc the terms of path W of C_mu(x) (over nu, sg) whose step J is the
 // link (y, lnu) given by coordinates y.
-template <typename T, int W, int J>
-__device__ __forceinline__ void path_term(const Geom &g, const Links<T> &L, const Links<T> &GC, const int y[4],
+template <typename T, int W, int J, class LD>
+__device__ __forceinline__ void path_term(const Geom &g, const LD &L, const Links<T> &GC, const int y[4],
                                           int lnu, int mu, int nu, int sg, T wt, M3<T> &acc) {
   using P = Path<W>;
   const int dJ = P::sym[J] ? nu : mu;
@@ -282,7 +282,7 @@ __device__ __forceinline__ void path_term(const Geom &g, const Links<T> &L, cons
   // walk from x: factors before and after step J
   M3<T> pre, post;
   int pos[4] = {x[0], x[1], x[2], x[3]};
-  walk_path<T, W, J, 0>(g, L, pos, mu, nu, sg, pre, post);
+  walk_path<T, W, J, 0, LD>(g, L, pos, mu, nu, sg, pre, post);
   const M3<T> gc = GC.at(g, x, mu);
   M3<T> term;  // pre^dag gc post^dag, an empty side being the identity
   if constexpr (J == 0) term = mul_nd(gc, post);
@@ -299,26 +299,29 @@ __device__ __forceinline__ void path_term(const Geom &g, const Links<T> &L, cons
   }
 }
 
-template <typename T, int W>
-__device__ __forceinline__ void path_terms(const Geom &g, const Links<T> &L, const Links<T> &GC, const int y[4],
+template <typename T, int W, class LD>
+__device__ __forceinline__ void path_terms(const Geom &g, const LD &L, const Links<T> &GC, const int y[4],
                                            int lnu, int mu, int nu, int sg, T wt, M3<T> &acc) {
-  path_term<T, W, 0>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  path_term<T, W, 1>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  path_term<T, W, 2>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
+  path_term<T, W, 0, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
+  path_term<T, W, 1, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
+  path_term<T, W, 2, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
   if (Path<W>::n == 5) {
-    path_term<T, W, (Path<W>::n == 5 ? 3 : 0)>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-    path_term<T, W, (Path<W>::n == 5 ? 4 : 0)>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
+    path_term<T, W, (Path<W>::n == 5 ? 3 : 0), LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
+    path_term<T, W, (Path<W>::n == 5 ? 4 : 0), LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
   }
 }
 
+// U12: the links of U as their first two rows (the path factors; row 2 rebuilt as conj(r0 x r1)),
+// two thirds of the bytes of the full matrices that each path term loads four of
 template <typename T, bool OI>
-__global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U,
+__global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U12,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = (w >> 3) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
   const int lnu = (w & 7) >> 1, par = w & 1;
-  const Links<T> L{const_cast<V2<T> *>(U), g.Vh}, GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};
+  const Links12<T> L{const_cast<V2<T> *>(U12), g.Vh};
+  const Links<T> GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};
   int y[4];
   coords_of(g, par, h, y);
   M3<T> acc = GU.load(lnu, par, h);
@@ -327,11 +330,11 @@ __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restr
     for (int nu = 0; nu < 4; nu++) {
       if (nu == mu) continue;
       for (int sg = 1; sg >= -1; sg -= 2) {
-        path_terms<T, 0>(g, L, GC, y, lnu, mu, nu, sg, wtp, acc);
+        path_terms<T, 0, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtp, acc);
         if (OI) {
-          path_terms<T, 1>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
-          path_terms<T, 2>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
-          path_terms<T, 3>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
+          path_terms<T, 1, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
+          path_terms<T, 2, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
+          path_terms<T, 3, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
         }
       }
     }

@@ -122,7 +122,8 @@ hipError_t launch_zero(double *p, int n, hipStream_t s);
 
 // k_backward.hip -- adjoint of one smearing step and the loss seed.
 // Seed: per-block sums of |tr W|^2 into part (field_blocks256 entries).
-// Step: per-block (dL/drho, dL/deps) pairs into part[0 .. 2 nb) and, for
+// Step (U12: scratch for U's links as two rows, the path factors of the gather):
+// per-block (dL/drho, dL/deps) pairs into part[0 .. 2 nb) and, for
 // eps = 1, the rectangle part of dL/deps into part[2 nb .. 3 nb), with
 // nb = adjoint_blocks(g); *flag is set if an exponent lies outside the
 // range of the unscaled series.
@@ -131,7 +132,7 @@ template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
                             hipStream_t s);
 template <typename T>
-hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, double rho,
-                               double eps, double *part, int *flag, hipStream_t s);
+hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, void *U12,
+                               double rho, double eps, double *part, int *flag, hipStream_t s);
 
 }  // namespace mcg
