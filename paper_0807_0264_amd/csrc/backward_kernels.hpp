@@ -16,7 +16,7 @@
 //   path terms: factor j of a path gets w (V_1..V_{j-1})^dag grad_C (V_{j+1}..V_k)^dag,
 //   or its dagger when the path walks that link backwards.
 // Pass A computes everything per link and stores grad_C; pass B gathers, for
-// every link, the path terms of all staples that contain it (no atomics).
+// every link, the path terms of all staples that contain it (no atomics), loop by loop.
 #pragma once
 
 #include "internal.hpp"
@@ -192,153 +192,130 @@ __global__ __launch_bounds__(128) void k_eps_rect(Geom g, const V2<T> *__restric
 }
 
 // --------------------------------------------------------------- pass B
-// Staple paths of C_mu(x), from x to x+mu, as steps over two symbols:
-// M = +mu and N = sg * nu (nu != mu, sg = +-1).
-//   W0: N  M  -N            (plaquette)
-//   W1: N  M  M  -N -M      (2x1 ahead)
-//   W2: -M N  M  M  -N      (2x1 behind)
-//   W3: N  N  M  -N -N      (1x2)
-template <int W> struct Path;
-template <> struct Path<0> {
-  static constexpr int n = 3;
-  static constexpr int sym[3] = {1, 0, 1};   // 0 = M, 1 = N
-  static constexpr int sgn[3] = {+1, +1, -1};
+// A staple term of C reaches a link through a closed loop: an output link l together with one of
+// its staple paths.  Every such loop through a target link m = U_lam(y) is traversed here from m
+// forwards, f_1 = m, f_2, ..., f_k (each a link or its dagger); the output link at position i
+// (i >= 2) sends m the term w (f_2 .. f_{i-1} Gam_i f_{i+1} .. f_k)^dag, Gam_i being grad_C of
+// that link, daggered when the loop walks it backwards (the factors of l's staple path before and
+// after m, as the chain rule gives them, rearranged around the loop).  Summed over i the terms are
+// the derivative of the product f_2 .. f_k along (Gam_2, .., Gam_k), built from the left with
+// A <- A f_i + P Gam_i, P <- P f_i: 3k - 7 products and 2(k - 1) loads per loop instead of a
+// product of the other k - 2 factors for each of the k - 1 outputs.
+// Loops through U_lam(y) in the (lam, nu) plane for sg = +-1, as steps over L = +lam, N = sg nu:
+//   S0: L  N -L -N          (plaquette: the stout staples)
+//   S1: L  L  N -L -L -N    (2x1, m the first of the two links along lam)
+//   S2: L  N -L -L -N  L    (2x1, m the second)
+//   S3: L  N  N -L -N -N    (1x2)
+// With the three other directions nu and both signs these are the 6 plaquettes and 18 rectangles
+// that contain m, one per staple of each of their other links.
+template <int S> struct Loop;
+template <> struct Loop<0> {
+  static constexpr int n = 4;
+  static constexpr int sym[4] = {0, 1, 0, 1};  // 0 = L, 1 = N
+  static constexpr int sgn[4] = {+1, +1, -1, -1};
 };
-template <> struct Path<1> {
-  static constexpr int n = 5;
-  static constexpr int sym[5] = {1, 0, 0, 1, 0};
-  static constexpr int sgn[5] = {+1, +1, +1, -1, -1};
+template <> struct Loop<1> {
+  static constexpr int n = 6;
+  static constexpr int sym[6] = {0, 0, 1, 0, 0, 1};
+  static constexpr int sgn[6] = {+1, +1, +1, -1, -1, -1};
 };
-template <> struct Path<2> {
-  static constexpr int n = 5;
-  static constexpr int sym[5] = {0, 1, 0, 0, 1};
-  static constexpr int sgn[5] = {-1, +1, +1, +1, -1};
+template <> struct Loop<2> {
+  static constexpr int n = 6;
+  static constexpr int sym[6] = {0, 1, 0, 0, 1, 0};
+  static constexpr int sgn[6] = {+1, +1, -1, -1, -1, +1};
 };
-template <> struct Path<3> {
-  static constexpr int n = 5;
-  static constexpr int sym[5] = {1, 1, 0, 1, 1};
-  static constexpr int sgn[5] = {+1, +1, +1, -1, -1};
+template <> struct Loop<3> {
+  static constexpr int n = 6;
+  static constexpr int sym[6] = {0, 1, 1, 0, 1, 1};
+  static constexpr int sgn[6] = {+1, +1, +1, -1, -1, -1};
 };
 
-// The factor of step K of path W (K != J) joins the product before step J
-// (pre) or after it (post); the first factor of each side is taken as it is
-// (a product with the identity would cost a full 3x3 product: it cannot be
-// folded away, because of signed zeros).
-template <typename T, int K, int J>
-__device__ __forceinline__ void take_factor(M3<T> &pre, M3<T> &post, const M3<T> &f, bool dagger) {
-  if constexpr (K < J) {
-    if constexpr (K == 0) pre = dagger ? dag(f) : f;
-    else pre = dagger ? mul_nd(pre, f) : mul(pre, f);
-  } else {
-    if constexpr (K == J + 1) post = dagger ? dag(f) : f;
-    else post = dagger ? mul_nd(post, f) : mul(post, f);
-  }
+// a b, or a b^dag
+template <bool DAG, typename T> __device__ __forceinline__ M3<T> mul_o(const M3<T> &a, const M3<T> &b) {
+  if constexpr (DAG) return mul_nd(a, b);
+  else return mul(a, b);
 }
 
-// Walk path W from pos, step K onwards, collecting the factors of every step but J.
-template <typename T, int W, int J, int K, class LD>
-__device__ __forceinline__ void walk_path(const Geom &g, const LD &L, int pos[4], int mu, int nu, int sg,
-                                          M3<T> &pre, M3<T> &post) {
-  if constexpr (K < Path<W>::n) {
-    constexpr int sym = Path<W>::sym[K], sgn = Path<W>::sgn[K];
-    const int d = sym ? nu : mu, s = sym ? sgn * sg : sgn;
+// Step K (>= 1) of loop S (sign SG) from pos: load f_K and Gam_K, advance the recurrence, move on.
+// The sign is a template argument, so every dagger is known when the kernel is compiled.
+template <typename T, int S, int SG, int K, class LD>
+__device__ __forceinline__ void loop_step(const Geom &g, const LD &L, const Links<T> &GC, const int pos[4],
+                                          int lam, int nu, M3<T> &A, M3<T> &P) {
+  if constexpr (K < Loop<S>::n) {
+    constexpr int sym = Loop<S>::sym[K], sgn = Loop<S>::sgn[K];
+    constexpr bool back = (sym ? sgn * SG : sgn) < 0;
+    const int d = sym ? nu : lam;
     int t[4];
-    if (s > 0) {
-      if constexpr (K != J) take_factor<T, K, J>(pre, post, L.at(g, pos, d), false);
-      moved(g, pos, d, +1, t);
+    moved(g, pos, d, back ? -1 : +1, t);
+    const int *at = back ? t : pos;
+    const M3<T> f = L.at(g, at, d);
+    const M3<T> G = GC.at(g, at, d);
+    if constexpr (K == 1) {
+      if constexpr (back) {
+        A = dag(G);
+        P = dag(f);
+      } else {
+        A = G;
+        P = f;
+      }
     } else {
-      moved(g, pos, d, -1, t);
-      if constexpr (K != J) take_factor<T, K, J>(pre, post, L.at(g, t, d), true);
+      M3<T> a = mul_o<back>(A, f);
+      add_to(mul_o<back>(P, G), a);
+      A = a;
+      if constexpr (K + 1 < Loop<S>::n) P = mul_o<back>(P, f);
     }
-#pragma unroll
-    for (int q = 0; q < 4; q++) pos[q] = t[q];
-    walk_path<T, W, J, K + 1, LD>(g, L, pos, mu, nu, sg, pre, post);
+    loop_step<T, S, SG, K + 1, LD>(g, L, GC, t, lam, nu, A, P);
   }
 }
 
-// Add to acc the terms of path W of C_mu(x) (over nu, sg) whose step J is the
-// link (y, lnu) given by coordinates y.
-template <typename T, int W, int J, class LD>
-__device__ __forceinline__ void path_term(const Geom &g, const LD &L, const Links<T> &GC, const int y[4],
-                                          int lnu, int mu, int nu, int sg, T wt, M3<T> &acc) {
-  using P = Path<W>;
-  const int dJ = P::sym[J] ? nu : mu;
-  if (dJ != lnu) return;
-  const int sJ = P::sym[J] ? P::sgn[J] * sg : P::sgn[J];
-  // start of the path: undo the steps before J (and the backward step itself)
-  int x[4] = {y[0], y[1], y[2], y[3]};
-  if (sJ < 0) {
-    int t[4];
-    moved(g, x, dJ, +1, t);
-    for (int k = 0; k < 4; k++) x[k] = t[k];
-  }
+// acc += w D^dag for loop S through U_lam(y) in direction nu, sign SG
+template <typename T, int S, int SG, class LD>
+__device__ __forceinline__ void loop_terms(const Geom &g, const LD &L, const Links<T> &GC, const int y[4], int lam,
+                                           int nu, T w, M3<T> &acc) {
+  int pos[4];
+  moved(g, y, lam, +1, pos);
+  // opaque start: keeps the compiler from computing the addresses of every loop at once (a
+  // register-pressure hint with no run-time cost)
+#if defined(__HIP_DEVICE_COMPILE__)
 #pragma unroll
-  for (int k = J - 1; k >= 0; k--) {
-    const int d = P::sym[k] ? nu : mu, s = P::sym[k] ? P::sgn[k] * sg : P::sgn[k];
-    int t[4];
-    moved(g, x, d, -s, t);
-    for (int q = 0; q < 4; q++) x[q] = t[q];
-  }
-  // walk from x: factors before and after step J
-  M3<T> pre, post;
-  int pos[4] = {x[0], x[1], x[2], x[3]};
-  walk_path<T, W, J, 0, LD>(g, L, pos, mu, nu, sg, pre, post);
-  const M3<T> gc = GC.at(g, x, mu);
-  M3<T> term;  // pre^dag gc post^dag, an empty side being the identity
-  if constexpr (J == 0) term = mul_nd(gc, post);
-  else if constexpr (J == P::n - 1) term = mul_dn(pre, gc);
-  else term = mul_nd(mul_dn(pre, gc), post);
-  if (sJ > 0) {
+  for (int q = 0; q < 4; q++) __asm__ volatile("" : "+v"(pos[q]));
+#endif
+  M3<T> A, P;
+  loop_step<T, S, SG, 1, LD>(g, L, GC, pos, lam, nu, A, P);
 #pragma unroll
-    for (int k = 0; k < 9; k++) acc.e[k] = acc.e[k] + wt * term.e[k];
-  } else {
+  for (int i = 0; i < 3; i++)
 #pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-      for (int j = 0; j < 3; j++) acc.e[3 * i + j] = acc.e[3 * i + j] + wt * conj(term.e[3 * j + i]);
-  }
+    for (int j = 0; j < 3; j++) acc.e[3 * i + j] = acc.e[3 * i + j] + w * conj(A.e[3 * j + i]);
 }
 
-template <typename T, int W, class LD>
-__device__ __forceinline__ void path_terms(const Geom &g, const LD &L, const Links<T> &GC, const int y[4],
-                                           int lnu, int mu, int nu, int sg, T wt, M3<T> &acc) {
-  path_term<T, W, 0, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  path_term<T, W, 1, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  path_term<T, W, 2, LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  if (Path<W>::n == 5) {
-    path_term<T, W, (Path<W>::n == 5 ? 3 : 0), LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-    path_term<T, W, (Path<W>::n == 5 ? 4 : 0), LD>(g, L, GC, y, lnu, mu, nu, sg, wt, acc);
-  }
-}
-
-// U12: the links of U as their first two rows (the path factors; row 2 rebuilt as conj(r0 x r1)),
-// two thirds of the bytes of the full matrices that each path term loads four of
+// U12: the links of U as their first two rows (the loop factors; row 2 rebuilt as conj(r0 x r1))
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U12,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = (w >> 3) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
-  const int lnu = (w & 7) >> 1, par = w & 1;
+  const int lam = (w & 7) >> 1, par = w & 1;
   const Links12<T> L{const_cast<V2<T> *>(U12), g.Vh};
   const Links<T> GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};
   int y[4];
   coords_of(g, par, h, y);
-  M3<T> acc = GU.load(lnu, par, h);
+  M3<T> acc = GU.load(lam, par, h);
   const T wtp = rho * wp, wtr = rho * wr;
-  for (int mu = 0; mu < 4; mu++)
-    for (int nu = 0; nu < 4; nu++) {
-      if (nu == mu) continue;
-      for (int sg = 1; sg >= -1; sg -= 2) {
-        path_terms<T, 0, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtp, acc);
-        if (OI) {
-          path_terms<T, 1, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
-          path_terms<T, 2, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
-          path_terms<T, 3, Links12<T>>(g, L, GC, y, lnu, mu, nu, sg, wtr, acc);
-        }
-      }
+  for (int nu = 0; nu < 4; nu++) {
+    if (nu == lam) continue;
+    loop_terms<T, 0, +1, Links12<T>>(g, L, GC, y, lam, nu, wtp, acc);
+    loop_terms<T, 0, -1, Links12<T>>(g, L, GC, y, lam, nu, wtp, acc);
+    if (OI) {
+      loop_terms<T, 1, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 1, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 2, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 2, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 3, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 3, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
     }
-  GU.store(lnu, par, h, acc);
+  }
+  GU.store(lam, par, h, acc);
 }
 
 }  // namespace mcg
