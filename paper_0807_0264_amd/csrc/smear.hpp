@@ -123,6 +123,16 @@ template <typename T> __device__ __forceinline__ M3<T> exp_su3(const M3<T> &A) {
 // product: the 2x1-behind and 1x2 paths of one nu and sign both end on the
 // link into x+mu along nu, and every 2x1-ahead path ends on U_mu(x+mu)^dag, so
 // their prefixes are summed first and multiplied by that link once.
+// Make the compiler treat coordinates as freshly produced (see staples).
+__device__ __forceinline__ void opaque_coords(int c[4]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int q = 0; q < 4; q++) __asm__ volatile("" : "+v"(c[q]));
+#else
+  (void)c;
+#endif
+}
+
 template <typename T, bool OI>
 __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const int c[4], int mu,
                                         M3<T> &Cp, M3<T> &Cr) {
@@ -132,58 +142,78 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
   int cpm[4], cmm[4];
   moved(g, c, mu, +1, cpm);
   moved(g, c, mu, -1, cmm);
+  const M3<T> umu_xmm = OI ? L.at(g, cmm, mu) : m_zero<T>();  // U_mu(x-mu)
   for (int nu = 0; nu < 4; nu++) {
     if (nu == mu) continue;
-    int cpn[4], cmn[4], cmnpm[4];
-    moved(g, c, nu, +1, cpn);
-    moved(g, c, nu, -1, cmn);
-    moved(g, cmn, mu, +1, cmnpm);
-    const M3<T> unu_x = L.at(g, c, nu);       // U_nu(x)
-    const M3<T> umu_xpn = L.at(g, cpn, mu);   // U_mu(x+nu)
-    const M3<T> unu_xpm = L.at(g, cpm, nu);   // U_nu(x+mu)
-    const M3<T> unu_xmn = L.at(g, cmn, nu);   // U_nu(x-nu)
-    const M3<T> umu_xmn = L.at(g, cmn, mu);   // U_mu(x-nu)
-    const M3<T> unu_xmnpm = L.at(g, cmnpm, nu);  // U_nu(x-nu+mu)
-    const M3<T> up = mul(unu_x, umu_xpn);     // U_nu(x) U_mu(x+nu)
-    const M3<T> dn = mul_dn(unu_xmn, umu_xmn);  // U_nu(x-nu)^dag U_mu(x-nu)
-    add_to(mul_nd(up, unu_xpm), Cp);
-    add_to(mul(dn, unu_xmnpm), Cp);
-    if (OI) {
-      int cpnpm[4], cp2m[4], cmmpn[4], cp2n[4], cmnp2m[4], cmmmn[4], cm2n[4], cm2npm[4];
-      moved(g, cpn, mu, +1, cpnpm);
-      moved(g, cpm, mu, +1, cp2m);
-      moved(g, cmm, nu, +1, cmmpn);
-      moved(g, cpn, nu, +1, cp2n);
-      moved(g, cmnpm, mu, +1, cmnp2m);
-      moved(g, cmm, nu, -1, cmmmn);
-      moved(g, cmn, nu, -1, cm2n);
-      moved(g, cm2n, mu, +1, cm2npm);
-      const M3<T> umu_xmm = L.at(g, cmm, mu);  // U_mu(x-mu)
-      M3<T> t, end;
-      // +nu, 2x1 ahead: U_nu(x) U_mu(x+nu) U_mu(x+nu+mu) U_nu(x+2mu)^dag [U_mu(x+mu)^dag]
-      t = mul(up, L.at(g, cpnpm, mu));
-      add_to(mul_nd(t, L.at(g, cp2m, nu)), ahead);
-      // +nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) [U_nu(x+mu)^dag]
-      t = mul_dn(umu_xmm, L.at(g, cmm, nu));
-      t = mul(t, L.at(g, cmmpn, mu));
-      end = mul(t, umu_xpn);
-      // +nu, 1x2: U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag [U_nu(x+mu)^dag]
-      t = mul(unu_x, L.at(g, cpn, nu));
-      t = mul(t, L.at(g, cp2n, mu));
-      add_to(mul_nd(t, L.at(g, cpnpm, nu)), end);
-      add_to(mul_nd(end, unu_xpm), Cr);
-      // -nu, 2x1 ahead: U_nu(x-nu)^dag U_mu(x-nu) U_mu(x-nu+mu) U_nu(x-nu+2mu) [U_mu(x+mu)^dag]
-      t = mul(dn, L.at(g, cmnpm, mu));
-      add_to(mul(t, L.at(g, cmnp2m, nu)), ahead);
-      // -nu, 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_mu(x-nu) [U_nu(x-nu+mu)]
-      t = dag(mul(L.at(g, cmmmn, nu), umu_xmm));
-      t = mul(t, L.at(g, cmmmn, mu));
-      end = mul(t, umu_xmn);
-      // -nu, 1x2: U_nu(x-nu)^dag U_nu(x-2nu)^dag U_mu(x-2nu) U_nu(x-2nu+mu) [U_nu(x-nu+mu)]
-      t = dag(mul(L.at(g, cm2n, nu), unu_xmn));
-      t = mul(t, L.at(g, cm2n, mu));
-      add_to(mul(t, L.at(g, cm2npm, nu)), end);
-      add_to(mul(end, unu_xmnpm), Cr);
+    // Each side of the direction starts from opaque copies of the base coordinates, so the
+    // compiler forms its addresses and loads where they are used rather than all at once (a
+    // register-pressure hint with no run-time cost); the sums are taken in the same order.
+    {  // +nu
+      int b[4] = {c[0], c[1], c[2], c[3]}, bpm[4] = {cpm[0], cpm[1], cpm[2], cpm[3]},
+          bmm[4] = {cmm[0], cmm[1], cmm[2], cmm[3]};
+      opaque_coords(b);
+      opaque_coords(bpm);
+      opaque_coords(bmm);
+      int cpn[4];
+      moved(g, b, nu, +1, cpn);
+      const M3<T> unu_x = L.at(g, b, nu);       // U_nu(x)
+      const M3<T> umu_xpn = L.at(g, cpn, mu);   // U_mu(x+nu)
+      const M3<T> unu_xpm = L.at(g, bpm, nu);   // U_nu(x+mu)
+      const M3<T> up = mul(unu_x, umu_xpn);     // U_nu(x) U_mu(x+nu)
+      add_to(mul_nd(up, unu_xpm), Cp);
+      if (OI) {
+        int cpnpm[4], cp2m[4], cmmpn[4], cp2n[4];
+        moved(g, cpn, mu, +1, cpnpm);
+        moved(g, bpm, mu, +1, cp2m);
+        moved(g, bmm, nu, +1, cmmpn);
+        moved(g, cpn, nu, +1, cp2n);
+        M3<T> t, end;
+        // 2x1 ahead: U_nu(x) U_mu(x+nu) U_mu(x+nu+mu) U_nu(x+2mu)^dag [U_mu(x+mu)^dag]
+        t = mul(up, L.at(g, cpnpm, mu));
+        add_to(mul_nd(t, L.at(g, cp2m, nu)), ahead);
+        // 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) [U_nu(x+mu)^dag]
+        t = mul_dn(umu_xmm, L.at(g, bmm, nu));
+        t = mul(t, L.at(g, cmmpn, mu));
+        end = mul(t, umu_xpn);
+        // 1x2: U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag [U_nu(x+mu)^dag]
+        t = mul(unu_x, L.at(g, cpn, nu));
+        t = mul(t, L.at(g, cp2n, mu));
+        add_to(mul_nd(t, L.at(g, cpnpm, nu)), end);
+        add_to(mul_nd(end, unu_xpm), Cr);
+      }
+    }
+    {  // -nu
+      int b[4] = {c[0], c[1], c[2], c[3]}, bmm[4] = {cmm[0], cmm[1], cmm[2], cmm[3]};
+      opaque_coords(b);
+      opaque_coords(bmm);
+      int cmn[4], cmnpm[4];
+      moved(g, b, nu, -1, cmn);
+      moved(g, cmn, mu, +1, cmnpm);
+      const M3<T> unu_xmn = L.at(g, cmn, nu);      // U_nu(x-nu)
+      const M3<T> umu_xmn = L.at(g, cmn, mu);      // U_mu(x-nu)
+      const M3<T> unu_xmnpm = L.at(g, cmnpm, nu);  // U_nu(x-nu+mu)
+      const M3<T> dn = mul_dn(unu_xmn, umu_xmn);   // U_nu(x-nu)^dag U_mu(x-nu)
+      add_to(mul(dn, unu_xmnpm), Cp);
+      if (OI) {
+        int cmnp2m[4], cmmmn[4], cm2n[4], cm2npm[4];
+        moved(g, cmnpm, mu, +1, cmnp2m);
+        moved(g, bmm, nu, -1, cmmmn);
+        moved(g, cmn, nu, -1, cm2n);
+        moved(g, cm2n, mu, +1, cm2npm);
+        M3<T> t, end;
+        // 2x1 ahead: U_nu(x-nu)^dag U_mu(x-nu) U_mu(x-nu+mu) U_nu(x-nu+2mu) [U_mu(x+mu)^dag]
+        t = mul(dn, L.at(g, cmnpm, mu));
+        add_to(mul(t, L.at(g, cmnp2m, nu)), ahead);
+        // 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_mu(x-nu) [U_nu(x-nu+mu)]
+        t = dag(mul(L.at(g, cmmmn, nu), umu_xmm));
+        t = mul(t, L.at(g, cmmmn, mu));
+        end = mul(t, umu_xmn);
+        // 1x2: U_nu(x-nu)^dag U_nu(x-2nu)^dag U_mu(x-2nu) U_nu(x-2nu+mu) [U_nu(x-nu+mu)]
+        t = dag(mul(L.at(g, cm2n, nu), unu_xmn));
+        t = mul(t, L.at(g, cm2n, mu));
+        add_to(mul(t, L.at(g, cm2npm, nu)), end);
+        add_to(mul(end, unu_xmnpm), Cr);
+      }
     }
   }
   if (OI) add_to(mul_nd(ahead, L.at(g, cpm, mu)), Cr);  // ... U_mu(x+mu)^dag
