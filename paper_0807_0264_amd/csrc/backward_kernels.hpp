@@ -99,13 +99,20 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
     coords_of(g, par, h, c);
     M3<T> Cp, Cr;
     staples<T, OI>(g, L, c, mu, Cp, Cr);
-    M3<T> Cu, C;
+    // only C and dC/deps stay live through the adjoint of the exponential (C = rho Cu)
+    M3<T> C, dC;
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-      Cu.e[k] = OI ? wp * Cp.e[k] + wr * Cr.e[k] : wp * Cp.e[k];
-      C.e[k] = rho * Cu.e[k];
+      const cx<T> cu = OI ? wp * Cp.e[k] + wr * Cr.e[k] : wp * Cp.e[k];
+      C.e[k] = rho * cu;
+      dC.e[k] = OI ? rho * (T(-2.0 / 3.0) * Cp.e[k] + T(1.0 / 12.0) * Cr.e[k]) : rho * T(-2.0 / 3.0) * Cp.e[k];
     }
-    const M3<T> u = L.load(mu, par, h);
+    // u and grad_U' load from an opaque index, so they are not held through the staple sum
+    int ho = h;
+#if defined(__HIP_DEVICE_COMPILE__)
+    __asm__ volatile("" : "+v"(ho));
+#endif
+    const M3<T> u = L.load(mu, par, ho);
     const M3<T> Q = minus_i(ta(mul_nd(C, u)));
     const M3<T> Q2 = mul(Q, Q);
     T c0, c1;
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
     E.e[4] = E.e[4] + co.f[0];
     E.e[8] = E.e[8] + co.f[0];
 
-    const M3<T> go = Links<T>{const_cast<V2<T> *>(gOut), g.Vh}.load(mu, par, h);
+    const M3<T> go = Links<T>{const_cast<V2<T> *>(gOut), g.Vh}.load(mu, par, ho);
     const M3<T> Gam = mul_nd(go, u);  // grad_E
     // tr(Gam^dag Q^j), j = 0, 1, 2
     const cx<T> t0 = conj(trace(Gam)), t1 = trdot(Gam, Q), t2 = trdot(Gam, Q2);
@@ -146,18 +153,11 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
     const M3<T> gc = mul(gOm, u);
     Links<T>{gU, g.Vh}.store(mu, par, h, gu);
     Links<T>{gC, g.Vh}.store(mu, par, h, gc);
-    drho = (double)rdot(gc, Cu);
-    if (OI) {
-      M3<T> dC;
-#pragma unroll
-      for (int k = 0; k < 9; k++) dC.e[k] = rho * (T(-2.0 / 3.0) * Cp.e[k] + T(1.0 / 12.0) * Cr.e[k]);
-      deps = (double)rdot(gc, dC);
-    } else {
-      // eps = 1: Cr is not formed here; its term is added by the rectangle-only
-      // kernel launched for the derivative in eps (see k_eps_rect)
-      M3<T> dC = scale(rho * T(-2.0 / 3.0), Cp);
-      deps = (double)rdot(gc, dC);
-    }
+    // d/drho of C is C / rho (Cu, the unscaled sum)
+    drho = (double)rdot(gc, C) / (double)rho;
+    // eps = 1 (stout): Cr is not formed here; its part of dC/deps is added by the rectangle-only
+    // kernel launched for the derivative in eps (see k_eps_rect)
+    deps = (double)rdot(gc, dC);
   }
   const double a = block_sum<128>(drho);
   const double b = block_sum<128>(deps);
