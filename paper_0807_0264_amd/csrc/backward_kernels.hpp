@@ -83,8 +83,11 @@ __global__ __launch_bounds__(256) void k_loss_seed(Geom g, const V2<T> *__restri
 // sums are stored by (direction and parity, tile), so their summation order does not depend on the
 // mapping.
 // --------------------------------------------------------------- pass A
+// Cst: the staple sums Cp (and Cr, OI) of U, stored by the smearing kernel (its CS modes), so that
+// the pass reads them instead of forming the staples again.
 template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restrict__ U,
+                                                    const V2<T> *__restrict__ Cst,
                                                     const V2<T> *__restrict__ gOut, V2<T> *__restrict__ gU,
                                                     V2<T> *__restrict__ gC, T rho, T wp, T wr, double *part,
                                                     int *flag) {
@@ -95,10 +98,9 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
   double drho = 0.0, deps = 0.0;
   if (h < g.Vh) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
-    int c[4];
-    coords_of(g, par, h, c);
-    M3<T> Cp, Cr;
-    staples<T, OI>(g, L, c, mu, Cp, Cr);
+    const M3<T> Cp = Links<T>{const_cast<V2<T> *>(Cst), g.Vh}.load(mu, par, h);
+    const M3<T> Cr = OI ? Links<T>{const_cast<V2<T> *>(Cst) + (size_t)72 * g.Vh, g.Vh}.load(mu, par, h)
+                        : m_zero<T>();
     // only C and dC/deps stay live through the adjoint of the exponential (C = rho Cu)
     M3<T> C, dC;
 #pragma unroll
@@ -107,12 +109,7 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
       C.e[k] = rho * cu;
       dC.e[k] = OI ? rho * (T(-2.0 / 3.0) * Cp.e[k] + T(1.0 / 12.0) * Cr.e[k]) : rho * T(-2.0 / 3.0) * Cp.e[k];
     }
-    // u and grad_U' load from an opaque index, so they are not held through the staple sum
-    int ho = h;
-#if defined(__HIP_DEVICE_COMPILE__)
-    __asm__ volatile("" : "+v"(ho));
-#endif
-    const M3<T> u = L.load(mu, par, ho);
+    const M3<T> u = L.load(mu, par, h);
     const M3<T> Q = minus_i(ta(mul_nd(C, u)));
     const M3<T> Q2 = mul(Q, Q);
     T c0, c1;
@@ -127,7 +124,7 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
     E.e[4] = E.e[4] + co.f[0];
     E.e[8] = E.e[8] + co.f[0];
 
-    const M3<T> go = Links<T>{const_cast<V2<T> *>(gOut), g.Vh}.load(mu, par, ho);
+    const M3<T> go = Links<T>{const_cast<V2<T> *>(gOut), g.Vh}.load(mu, par, h);
     const M3<T> Gam = mul_nd(go, u);  // grad_E
     // tr(Gam^dag Q^j), j = 0, 1, 2
     const cx<T> t0 = conj(trace(Gam)), t1 = trdot(Gam, Q), t2 = trdot(Gam, Q2);

@@ -70,11 +70,12 @@ template <typename T>
 hipError_t launch_plaquette(const Geom &g, const void *U, double *part, double *out, hipStream_t s);
 int field_blocks256(const Geom &g);
 
-// k_smear.hip -- one stout / over-improved stout step; sets *flag if an
-// exponent needed scaling beyond the series' range
+// k_smear.hip -- one stout / over-improved stout step U -> out.  With Cst, the staple sums of every
+// link are stored there too (field_bytes each: Cp, then Cr for eps != 1); c_only: only those, out
+// unused
 template <typename T>
 hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
-                             hipStream_t s);
+                             hipStream_t s, void *Cst = nullptr, bool c_only = false);
 
 // k_project.hip -- centre projection and vortex counting
 template <typename T>
@@ -131,8 +132,9 @@ int adjoint_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
                             hipStream_t s);
+// Cst: the staple sums of U as launch_smear_step stores them
 template <typename T>
-hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *gOut, void *gU, void *gC, void *U12,
-                               double rho, double eps, double *part, int *flag, hipStream_t s);
+hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
+                               void *U12, double rho, double eps, double *part, int *flag, hipStream_t s);
 
 }  // namespace mcg

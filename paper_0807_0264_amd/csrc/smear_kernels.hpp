@@ -6,9 +6,12 @@
 
 namespace mcg {
 
-template <typename T, bool OI>
+// CS = 1: also store the staple sums Cp (and Cr, OI) of every link in Cst, as two link fields
+// [Cp | Cr]; CS = 2: store them only (no smeared link), for the adjoint's first pass
+template <typename T, bool OI, int CS = 0>
 __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__ U,
-                                               V2<T> *__restrict__ out, T rho, T wp, T wr) {
+                                               V2<T> *__restrict__ out, T rho, T wp, T wr,
+                                               V2<T> *__restrict__ Cst = nullptr) {
   // one block per (tile, direction, parity); the eight blocks of a tile follow each other and each
   // XCD takes a contiguous range of tiles (xcd_range), so the staple links that the eight share,
   // and those of the next tiles along z and t, are still in that XCD's L2 or the last-level cache
@@ -21,6 +24,11 @@ __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__
   coords_of(g, par, h, c);
   M3<T> Cp, Cr;
   staples<T, OI>(g, L, c, mu, Cp, Cr);
+  if constexpr (CS != 0) {
+    Links<T>{Cst, g.Vh}.store(mu, par, h, Cp);
+    if (OI) Links<T>{Cst + (size_t)72 * g.Vh, g.Vh}.store(mu, par, h, Cr);
+  }
+  if constexpr (CS == 2) return;
   M3<T> C;
 #pragma unroll
   for (int k = 0; k < 9; k++) {
