@@ -442,7 +442,7 @@ mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, cons
  * as U) and host scalars L, dL/drho, dL/deps.  Smeared fields are
  * checkpointed every ckpt_every steps and recomputed between checkpoints.
  * Device workspace held by the context: with c = ckpt_every (n if <= 0 or
- * > n), ceil(n/c) + (c - 1) + 6 + c * (eps == 1 ? 1 : 2) fields of U's size
+ * > n), ceil(n/c) + (c - 1) + 5 + c * (eps == 1 ? 1 : 2) fields of U's size
  * (the checkpoints, one segment's fields and the staple sums of its steps). */
 mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps,
                                   int32_t n, const mcg_gauge *Gstar, int32_t ckpt_every,

@@ -285,15 +285,14 @@ __device__ __forceinline__ void loop_terms(const Geom &g, const LD &L, const Lin
     for (int j = 0; j < 3; j++) acc.e[3 * i + j] = acc.e[3 * i + j] + w * conj(A.e[3 * j + i]);
 }
 
-// U12: the links of U as their first two rows (the loop factors; row 2 rebuilt as conj(r0 x r1))
 template <typename T, bool OI>
-__global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U12,
+__global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = (w >> 3) * 128 + threadIdx.x;
   if (h >= g.Vh) return;
   const int lam = (w & 7) >> 1, par = w & 1;
-  const Links12<T> L{const_cast<V2<T> *>(U12), g.Vh};
+  const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
   const Links<T> GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};
   int y[4];
   coords_of(g, par, h, y);
@@ -301,15 +300,15 @@ __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restr
   const T wtp = rho * wp, wtr = rho * wr;
   for (int nu = 0; nu < 4; nu++) {
     if (nu == lam) continue;
-    loop_terms<T, 0, +1, Links12<T>>(g, L, GC, y, lam, nu, wtp, acc);
-    loop_terms<T, 0, -1, Links12<T>>(g, L, GC, y, lam, nu, wtp, acc);
+    loop_terms<T, 0, +1, Links<T>>(g, L, GC, y, lam, nu, wtp, acc);
+    loop_terms<T, 0, -1, Links<T>>(g, L, GC, y, lam, nu, wtp, acc);
     if (OI) {
-      loop_terms<T, 1, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 1, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 2, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 2, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 3, +1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 3, -1, Links12<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 1, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 1, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 2, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 2, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 3, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
+      loop_terms<T, 3, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
     }
   }
   GU.store(lam, par, h, acc);

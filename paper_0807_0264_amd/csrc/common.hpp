@@ -406,10 +406,6 @@ template <typename T> struct Links12 {
   __device__ __forceinline__ void store(int mu, int par, int h, const M3<T> &m) const {
     store_off(mu, off(par, h), m);
   }
-  // link mu at the site with coordinates c, row 2 rebuilt
-  __device__ __forceinline__ M3<T> at(const Geom &g, const int c[4], int mu) const {
-    return load(mu, parity_of(c), half_index(g, c));
-  }
 };
 
 // ----------------------------------------- products in a fixed FMA order

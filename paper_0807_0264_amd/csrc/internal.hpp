@@ -135,6 +135,6 @@ hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void 
 // Cst: the staple sums of U as launch_smear_step stores them
 template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
-                               void *U12, double rho, double eps, double *part, int *flag, hipStream_t s);
+                               double rho, double eps, double *part, int *flag, hipStream_t s);
 
 }  // namespace mcg

@@ -17,23 +17,21 @@ hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void 
 
 template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
-                               void *U12, double rho, double eps, double *part, int *flag, hipStream_t s) {
+                               double rho, double eps, double *part, int *flag, hipStream_t s) {
   if (!Cst) return hipErrorInvalidValue;
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
   const int grid = 8 * ((g.Vh + 127) / 128);
   const int nb = grid;
-  hipError_t e = launch_links_form<T>(g, U, U12, true, s);  // the path factors as two rows
-  if (e != hipSuccess) return e;
   if (eps == 1.0) {
     k_step_adj_a<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)Cst, (const V2<T> *)gOut,
                                                 (V2<T> *)gU, (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
     k_eps_rect<T><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (T)rho, part + 2 * nb);
-    k_step_adj_b<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U12, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
+    k_step_adj_b<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
                                                 (T)wp, (T)wr);
   } else {
     k_step_adj_a<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)Cst, (const V2<T> *)gOut,
                                                (V2<T> *)gU, (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
-    k_step_adj_b<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U12, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
+    k_step_adj_b<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
                                                (T)wp, (T)wr);
   }
   return hipGetLastError();
@@ -44,8 +42,8 @@ template hipError_t launch_loss_seed<float>(const Geom &, const void *, const do
 template hipError_t launch_loss_seed<double>(const Geom &, const void *, const double *, void *, double *,
                                              hipStream_t);
 template hipError_t launch_step_adjoint<float>(const Geom &, const void *, const void *, const void *, void *,
-                                               void *, void *, double, double, double *, int *, hipStream_t);
+                                               void *, double, double, double *, int *, hipStream_t);
 template hipError_t launch_step_adjoint<double>(const Geom &, const void *, const void *, const void *, void *,
-                                                void *, void *, double, double, double *, int *, hipStream_t);
+                                                void *, double, double, double *, int *, hipStream_t);
 
 }  // namespace mcg

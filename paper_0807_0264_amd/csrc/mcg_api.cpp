@@ -699,11 +699,10 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   const size_t fb = field_bytes(U->d, U->prec);
   const int c = (ckpt_every <= 0 || ckpt_every > n) ? std::max(n, 1) : ckpt_every;
   const int nck = n > 0 ? (n + c - 1) / c : 0;
-  // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C, the
-  // two-row copy of a step's input links (the adjoint's loop factors), and the staple sums of the c
-  // steps of a segment (Cp, and Cr for eps != 1)
+  // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C, and the
+  // staple sums of the c steps of a segment (Cp, and Cr for eps != 1)
   const int ncs = eps == 1.0 ? 1 : 2;
-  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 6 + (size_t)c * ncs;
+  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 5 + (size_t)c * ncs;
   mcg_status st;
   if ((st = ensure(ctx, ctx->ckpt, fb * nfields))) return st;
   const int nb_seed = field_blocks256(g), nb_step = adjoint_blocks(g);
@@ -712,8 +711,8 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   char *base = (char *)ctx->ckpt.p;
   auto slot = [&](size_t i) { return (void *)(base + i * fb); };
   void *tmp0 = slot(nck + c - 1), *tmp1 = slot(nck + c), *gA = slot(nck + c + 1), *gB = slot(nck + c + 2),
-       *gC = slot(nck + c + 3), *U12 = slot(nck + c + 4);
-  auto csum = [&](int j) { return slot((size_t)nck + c + 5 + (size_t)j * ncs); };  // step j of a segment
+       *gC = slot(nck + c + 3);
+  auto csum = [&](int j) { return slot((size_t)nck + c + 4 + (size_t)j * ncs); };  // step j of a segment
   double *part = (double *)ctx->bw_part.p;
   int *flag = (int *)(part + nparts);
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
@@ -745,7 +744,7 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
     for (int j = len - 1; j >= 0; j--) {
       const int k = k0 + j;
       double *p = part + nb_seed + (size_t)k * 3 * nb_step;
-      HIPCHK(launch_step_adjoint<T>(g, fields[j], csum(j), gin, gout, gC, U12, rho, eps, p, flag, s));
+      HIPCHK(launch_step_adjoint<T>(g, fields[j], csum(j), gin, gout, gC, rho, eps, p, flag, s));
       std::swap(gin, gout);
     }
   }
