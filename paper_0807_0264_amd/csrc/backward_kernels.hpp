@@ -233,12 +233,13 @@ template <bool DAG, typename T> __device__ __forceinline__ M3<T> mul_o(const M3<
   else return mul(a, b);
 }
 
-// Step K (>= 1) of loop S (sign SG) from pos: load f_K and Gam_K, advance the recurrence, move on.
-// The sign is a template argument, so every dagger is known when the kernel is compiled.
-template <typename T, int S, int SG, int K, class LD>
-__device__ __forceinline__ void loop_step(const Geom &g, const LD &L, const Links<T> &GC, const int pos[4],
-                                          int lam, int nu, M3<T> &A, M3<T> &P) {
-  if constexpr (K < Loop<S>::n) {
+// Steps K .. KEND-1 (K >= 1) of loop S (sign SG), from pos (left at the position after them): load
+// f_K and Gam_K, advance the recurrence.  The sign is a template argument, so every dagger is known
+// when the kernel is compiled.
+template <typename T, int S, int SG, int K, int KEND, class LD>
+__device__ __forceinline__ void loop_steps(const Geom &g, const LD &L, const Links<T> &GC, int pos[4], int lam,
+                                           int nu, M3<T> &A, M3<T> &P) {
+  if constexpr (K < KEND) {
     constexpr int sym = Loop<S>::sym[K], sgn = Loop<S>::sgn[K];
     constexpr bool back = (sym ? sgn * SG : sgn) < 0;
     const int d = sym ? nu : lam;
@@ -261,28 +262,65 @@ __device__ __forceinline__ void loop_step(const Geom &g, const LD &L, const Link
       A = a;
       if constexpr (K + 1 < Loop<S>::n) P = mul_o<back>(P, f);
     }
-    loop_step<T, S, SG, K + 1, LD>(g, L, GC, t, lam, nu, A, P);
+#pragma unroll
+    for (int q = 0; q < 4; q++) pos[q] = t[q];
+    loop_steps<T, S, SG, K + 1, KEND, LD>(g, L, GC, pos, lam, nu, A, P);
   }
 }
 
-// acc += w D^dag for loop S through U_lam(y) in direction nu, sign SG
-template <typename T, int S, int SG, class LD>
-__device__ __forceinline__ void loop_terms(const Geom &g, const LD &L, const Links<T> &GC, const int y[4], int lam,
-                                           int nu, T w, M3<T> &acc) {
-  int pos[4];
-  moved(g, y, lam, +1, pos);
-  // opaque start: keeps the compiler from computing the addresses of every loop at once (a
-  // register-pressure hint with no run-time cost)
-#if defined(__HIP_DEVICE_COMPILE__)
-#pragma unroll
-  for (int q = 0; q < 4; q++) __asm__ volatile("" : "+v"(pos[q]));
-#endif
-  M3<T> A, P;
-  loop_step<T, S, SG, 1, LD>(g, L, GC, pos, lam, nu, A, P);
+template <typename T> __device__ __forceinline__ void add_dag(T w, const M3<T> &A, M3<T> &acc) {
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = 0; j < 3; j++) acc.e[3 * i + j] = acc.e[3 * i + j] + w * conj(A.e[3 * j + i]);
+}
+
+// opaque copy of start coordinates: keeps the compiler from computing the addresses of every loop
+// at once (a register-pressure hint with no run-time cost)
+__device__ __forceinline__ void opaque_start(const int in[4], int out[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; q++) out[q] = in[q];
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int q = 0; q < 4; q++) __asm__ volatile("" : "+v"(out[q]));
+#endif
+}
+
+// The loops of one direction nu and sign SG through U_lam(y), added to acc with their weights.
+// S0, S2 and S3 leave m along N through the same link, and S0 and S2 go on along -L through the
+// same link too: those steps are taken once and the loops continue from copies of (A, P).
+template <typename T, bool OI, int SG, class LD>
+__device__ __forceinline__ void loops_of(const Geom &g, const LD &L, const Links<T> &GC, const int yl[4], int lam,
+                                         int nu, T wp, T wr, M3<T> &acc) {
+  M3<T> A, P;
+  {  // S1: L L N -L -L -N
+    if constexpr (OI) {
+      int pos[4];
+      opaque_start(yl, pos);
+      loop_steps<T, 1, SG, 1, 6, LD>(g, L, GC, pos, lam, nu, A, P);
+      add_dag(wr, A, acc);
+    }
+  }
+  int pos[4];
+  opaque_start(yl, pos);
+  loop_steps<T, 0, SG, 1, 2, LD>(g, L, GC, pos, lam, nu, A, P);  // N, shared by S0, S2, S3
+  if constexpr (OI) {  // S3: L N N -L -N -N
+    int p3[4];
+    opaque_start(pos, p3);
+    M3<T> A3 = A, P3 = P;
+    loop_steps<T, 3, SG, 2, 6, LD>(g, L, GC, p3, lam, nu, A3, P3);
+    add_dag(wr, A3, acc);
+  }
+  loop_steps<T, 0, SG, 2, 3, LD>(g, L, GC, pos, lam, nu, A, P);  // -L, shared by S0 and S2
+  if constexpr (OI) {  // S2: L N -L -L -N L
+    int p2[4];
+    opaque_start(pos, p2);
+    M3<T> A2 = A, P2 = P;
+    loop_steps<T, 2, SG, 3, 6, LD>(g, L, GC, p2, lam, nu, A2, P2);
+    add_dag(wr, A2, acc);
+  }
+  loop_steps<T, 0, SG, 3, 4, LD>(g, L, GC, pos, lam, nu, A, P);  // S0: L N -L -N
+  add_dag(wp, A, acc);
 }
 
 template <typename T, bool OI>
@@ -298,18 +336,12 @@ __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restr
   coords_of(g, par, h, y);
   M3<T> acc = GU.load(lam, par, h);
   const T wtp = rho * wp, wtr = rho * wr;
+  int yl[4];  // the end of m: every loop's walk starts there
+  moved(g, y, lam, +1, yl);
   for (int nu = 0; nu < 4; nu++) {
     if (nu == lam) continue;
-    loop_terms<T, 0, +1, Links<T>>(g, L, GC, y, lam, nu, wtp, acc);
-    loop_terms<T, 0, -1, Links<T>>(g, L, GC, y, lam, nu, wtp, acc);
-    if (OI) {
-      loop_terms<T, 1, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 1, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 2, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 2, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 3, +1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-      loop_terms<T, 3, -1, Links<T>>(g, L, GC, y, lam, nu, wtr, acc);
-    }
+    loops_of<T, OI, +1, Links<T>>(g, L, GC, yl, lam, nu, wtp, wtr, acc);
+    loops_of<T, OI, -1, Links<T>>(g, L, GC, yl, lam, nu, wtp, wtr, acc);
   }
   GU.store(lam, par, h, acc);
 }
