@@ -161,7 +161,7 @@ hipError_t launch_theta(int bs, bool c12, const void *D, int B, int blocks, hipS
 }
 
 template <typename T> hipError_t launch_book(const void *D, int B, int what, hipStream_t s) {
-  k_book<T><<<B, 256, 0, s>>>((const LatDesc<T> *)D, what);
+  k_book<T><<<B, 1024, 0, s>>>((const LatDesc<T> *)D, what);
   return hipGetLastError();
 }
 

@@ -677,10 +677,10 @@ __global__ __launch_bounds__(256) void k_gauge_form(Geom g, const double2 *__res
 // over the per-wavefront partials in index order (independent of the block size).
 enum { BK_INIT = 0, BK_RESET = 1, BK_CHECK = 2, BK_FINAL = 3, BK_THETA = 4, BK_FOLD = 5 };
 
-// 32 loads in flight per thread: the 16384 wave partials of a 32^3x64 half-lattice arrive in two
-// round trips (the sum is latency-bound, once per sweep).
+// 1024 threads with 16 loads in flight each: the 16384 wave partials of a 32^3x64 half-lattice
+// arrive in one round trip (the sum is latency-bound, once per sweep; 256 threads took two).
 template <typename T>
-__global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, int what) {
+__global__ __launch_bounds__(1024) void k_book(const LatDesc<T> *__restrict__ D, int what) {
   const LatDesc<T> d = D[blockIdx.x];
   FixState *st = d.st;
   if (what == BK_FOLD) {  // after k_fold: every sweep run so far is in G
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(256) void k_book(const LatDesc<T> *__restrict__ D, 
   // the state is read once, alongside the partial sums (the two loads do not wait for each
   // other); a finished field's block leaves after the sum, together (the exit is block-uniform)
   const FixState sv = *st;
-  const double s = sum_partials<256, 32>(d.part, d.npart);
+  const double s = sum_partials<1024, 16>(d.part, d.npart);
   if ((what == BK_RESET || what == BK_CHECK) && sv.done) return;
   if (threadIdx.x != 0) return;
   const double R = s / (9.0 * (double)(4 * d.g.V));
