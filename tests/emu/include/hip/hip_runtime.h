@@ -18,7 +18,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <mutex>
+#include <semaphore>
 #include <thread>
 #include <vector>
 
@@ -137,50 +139,48 @@ inline void submit(hipStream_t s, std::function<void()> f) {
     f();
 }
 // Persistent lane threads: run(n, f) calls f(t) on threads t = 0..n-1 and
-// returns when all have finished (threads are created once and reused).
+// returns when all have finished (threads are created once and reused; each
+// waits on its own semaphore, so a launch wakes only the lanes it uses).
 class LanePool {
  public:
+  static constexpr unsigned MAXLANES = 1024;  // the largest block HIP allows
   static LanePool &get() {
     static LanePool *p = new LanePool;  // never destroyed: idle workers may outlive main
     return *p;
   }
   void run(unsigned n, const std::function<void(unsigned)> &f) {
-    std::unique_lock<std::mutex> lk(m_);
-    while (th_.size() < n) {
-      const unsigned id = (unsigned)th_.size();
-      th_.emplace_back([this, id] { work(id); });
-      th_.back().detach();
+    if (n > MAXLANES) std::abort();
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      while (nth_ < n) {
+        const unsigned id = nth_++;
+        sem_[id] = std::make_unique<std::binary_semaphore>(0);
+        std::thread([this, id] { work(id); }).detach();
+      }
+      task_ = &f;
+      left_ = n;
     }
-    task_ = &f;
-    n_ = n;
-    left_ = n;
-    gen_++;
-    go_.notify_all();
+    for (unsigned t = 0; t < n; t++) sem_[t]->release();  // publishes task_ to lane t
+    std::unique_lock<std::mutex> lk(m_);
     done_.wait(lk, [this] { return left_ == 0; });
     task_ = nullptr;
   }
 
  private:
   void work(unsigned id) {
-    uint64_t seen = 0;
-    std::unique_lock<std::mutex> lk(m_);
     for (;;) {
-      go_.wait(lk, [&] { return gen_ != seen; });
-      seen = gen_;
-      if (id >= n_) continue;
+      sem_[id]->acquire();
       const std::function<void(unsigned)> *f = task_;
-      lk.unlock();
       (*f)(id);
-      lk.lock();
+      std::lock_guard<std::mutex> lk(m_);
       if (--left_ == 0) done_.notify_one();
     }
   }
   std::mutex m_;
-  std::condition_variable go_, done_;
-  std::vector<std::thread> th_;
+  std::condition_variable done_;
+  std::unique_ptr<std::binary_semaphore> sem_[MAXLANES];
   const std::function<void(unsigned)> *task_ = nullptr;
-  unsigned n_ = 0, left_ = 0;
-  uint64_t gen_ = 0;
+  unsigned nth_ = 0, left_ = 0;
 };
 
 template <typename F> void run_grid(dim3 grid, dim3 block, F body) {

@@ -285,7 +285,7 @@ def scenario_variants(prec):
     E.set_two_row(True)
 
 
-def scenario_defer():
+def scenario_defer(parts=("rows", "full", "fp64")):
     """FP32: the transform ring (each half-sweep's g folded into G later) gives
     the bits of updating G in every half-sweep, and paired sweeps (the first
     half-sweep leaves the links to the second) the bits of plain ones: a batch
@@ -295,7 +295,7 @@ def scenario_defer():
     L1, L2 = (4, 4, 4, 16), (4, 2, 2, 4)
     U1, U2 = rounded(field(L1, 2090), prec), rounded(field(L2, 2091), prec)
     G1 = S.haar_gauge(L1, S.sub_seed(2092))
-    for two_row in (True, False):
+    for two_row in [t for t, name in ((True, "rows"), (False, "full")) if name in parts]:
         E.set_two_row(two_row)
         got = []
         for defer, paired in ((True, True), (True, False), (False, True)):
@@ -318,6 +318,8 @@ def scenario_defer():
     E.set_paired(True)
     E.set_defer_g(True)
     E.set_two_row(True)
+    if "fp64" not in parts:
+        return
     # FP64 with paired = 2: the even g is handed over in a one-slot buffer, G updated in place
     U0 = field(L1, 2093)
     got = []
@@ -401,22 +403,26 @@ def main():
     lat = [(4, 4, 4, 4), (6, 4, 2, 4), (2, 2, 2, 2)]
     names = sys.argv[1:] or ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward",
                              "loops", "slabs", "variants", "checks", "defer"]
-    for name in names:
+    for arg in names:
+        # "group" runs all of it; "group:part" one part (a precision, or a part of defer), so that
+        # the long groups can run side by side
+        name, _, part = arg.partition(":")
+        precs = (int(part),) if part in ("0", "1") else (0, 1)
         if name == "batch":
-            for prec in (0, 1):
+            for prec in precs:
                 scenario_batch(prec)
         elif name == "planted":
             scenario_planted()
         elif name == "checks":
-            for prec in (0, 1):
+            for prec in precs:
                 scenario_checks(prec)
         elif name == "defer":
-            scenario_defer()
+            scenario_defer((part,) if part else ("rows", "full", "fp64"))
         elif name == "variants":
-            for prec in (0, 1):
+            for prec in precs:
                 scenario_variants(prec)
         elif name == "slabs":
-            for prec in (0, 1):
+            for prec in precs:
                 scenario_slabs(prec)
         elif name == "loops":
             for L in ((4, 4, 4, 4), (2, 2, 2, 2)):
@@ -430,7 +436,7 @@ def main():
             for L in lat:
                 for prec in (0, 1):
                     globals()["scenario_" + name](L, prec)
-        print("ok", name, flush=True)
+        print("ok", arg, flush=True)
 
 
 if __name__ == "__main__":

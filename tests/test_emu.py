@@ -10,8 +10,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "emu")
-GROUPS = ["fields", "smear", "halfsweep", "fix", "project", "batch", "planted", "backward", "loops",
-          "slabs", "variants", "checks", "defer"]
+# the long groups split by precision (or, for defer, by part) so that they run side by side
+GROUPS = ["fields", "smear", "halfsweep", "fix", "project", "batch:0", "batch:1", "planted", "backward", "loops",
+          "slabs:0", "slabs:1", "variants:0", "variants:1", "checks", "defer:rows", "defer:full", "defer:fp64"]
 
 
 def _stale(lib, srcdirs):
