@@ -71,11 +71,10 @@ hipError_t launch_plaquette(const Geom &g, const void *U, double *part, double *
 int field_blocks256(const Geom &g);
 
 // k_smear.hip -- one stout / over-improved stout step U -> out.  With Cst, the staple sums of every
-// link are stored there too (field_bytes each: Cp, then Cr for eps != 1); c_only: only those, out
-// unused
+// link are stored there too (field_bytes each: Cp, then Cr for eps != 1)
 template <typename T>
 hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
-                             hipStream_t s, void *Cst = nullptr, bool c_only = false);
+                             hipStream_t s, void *Cst = nullptr);
 
 // k_project.hip -- centre projection and vortex counting
 template <typename T>

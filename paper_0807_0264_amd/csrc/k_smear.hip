@@ -11,28 +11,26 @@ namespace mcg {
 
 template <typename T>
 hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
-                             hipStream_t s, void *Cst, bool c_only) {
+                             hipStream_t s, void *Cst) {
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
   const int grid = 8 * ((g.Vh + 127) / 128);
-  if ((c_only && !Cst) || (!c_only && !out)) return hipErrorInvalidValue;
+  if (!out) return hipErrorInvalidValue;
   const V2<T> *u = (const V2<T> *)U;
   V2<T> *o = (V2<T> *)out, *cs = (V2<T> *)Cst;
   const T r = (T)rho, p = (T)wp, q = (T)wr;
   if (eps == 1.0) {
-    if (c_only) k_smear<T, false, 2><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
-    else if (cs) k_smear<T, false, 1><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
+    if (cs) k_smear<T, false, 1><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
     else k_smear<T, false><<<grid, 128, 0, s>>>(g, u, o, r, p, q);
   } else {
-    if (c_only) k_smear<T, true, 2><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
-    else if (cs) k_smear<T, true, 1><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
+    if (cs) k_smear<T, true, 1><<<grid, 128, 0, s>>>(g, u, o, r, p, q, cs);
     else k_smear<T, true><<<grid, 128, 0, s>>>(g, u, o, r, p, q);
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_smear_step<float>(const Geom &, const void *, void *, double, double, hipStream_t,
-                                             void *, bool);
+                                             void *);
 template hipError_t launch_smear_step<double>(const Geom &, const void *, void *, double, double, hipStream_t,
-                                              void *, bool);
+                                              void *);
 
 }  // namespace mcg

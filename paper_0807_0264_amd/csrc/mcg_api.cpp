@@ -699,10 +699,11 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   const size_t fb = field_bytes(U->d, U->prec);
   const int c = (ckpt_every <= 0 || ckpt_every > n) ? std::max(n, 1) : ckpt_every;
   const int nck = n > 0 ? (n + c - 1) / c : 0;
-  // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C, and the
-  // staple sums of the c steps of a segment (Cp, and Cr for eps != 1)
+  // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C, the
+  // staple sums (Cp, and Cr for eps != 1) of the first c-1 steps of a segment, and those of every
+  // segment's last step, which the forward pass stores
   const int ncs = eps == 1.0 ? 1 : 2;
-  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 5 + (size_t)c * ncs;
+  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 5 + (size_t)(c - 1) * ncs + (size_t)nck * ncs;
   mcg_status st;
   if ((st = ensure(ctx, ctx->ckpt, fb * nfields))) return st;
   const int nb_seed = field_blocks256(g), nb_step = adjoint_blocks(g);
@@ -712,18 +713,20 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   auto slot = [&](size_t i) { return (void *)(base + i * fb); };
   void *tmp0 = slot(nck + c - 1), *tmp1 = slot(nck + c), *gA = slot(nck + c + 1), *gB = slot(nck + c + 2),
        *gC = slot(nck + c + 3);
-  auto csum = [&](int j) { return slot((size_t)nck + c + 4 + (size_t)j * ncs); };  // step j of a segment
+  auto csum = [&](int j) { return slot((size_t)nck + c + 4 + (size_t)j * ncs); };  // step j < c-1 of a segment
+  auto clast = [&](int seg) { return slot((size_t)nck + c + 4 + (size_t)(c - 1) * ncs + (size_t)seg * ncs); };
   double *part = (double *)ctx->bw_part.p;
   int *flag = (int *)(part + nparts);
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(part, 0, sizeof(double) * nparts, s));
 
-  // forward, keeping every c-th field
+  // forward, keeping every c-th field and the staple sums of each segment's last step
   const void *cur = U->ptr;
   for (int k = 0; k < n; k++) {
     if (k % c == 0) HIPCHK(hipMemcpyAsync(slot(k / c), cur, fb, hipMemcpyDeviceToDevice, s));
     void *nxt = (cur == tmp0) ? tmp1 : tmp0;
-    HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s));
+    const bool last = k % c == c - 1 || k == n - 1;
+    HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s, last ? clast(k / c) : nullptr));
     cur = nxt;
   }
   HIPCHK(launch_loss_seed<T>(g, cur, Gstar->ptr, gA, part, s));
@@ -731,8 +734,8 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   for (int seg = nck - 1; seg >= 0; seg--) {
     const int k0 = seg * c, len = std::min(c, n - k0);
     // the segment's fields again from its checkpoint, keeping the staple sums that each smearing
-    // step forms (the last step's from a staple-only launch of the same kernel), which the first
-    // pass of the adjoint reads
+    // step forms (the last step's were kept by the forward pass), which the first pass of the
+    // adjoint reads
     std::vector<const void *> fields(len);
     fields[0] = slot(seg);
     for (int j = 1; j < len; j++) {
@@ -740,11 +743,11 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
       HIPCHK(launch_smear_step<T>(g, fields[j - 1], dst, rho, eps, s, csum(j - 1)));
       fields[j] = dst;
     }
-    HIPCHK(launch_smear_step<T>(g, fields[len - 1], nullptr, rho, eps, s, csum(len - 1), true));
     for (int j = len - 1; j >= 0; j--) {
       const int k = k0 + j;
       double *p = part + nb_seed + (size_t)k * 3 * nb_step;
-      HIPCHK(launch_step_adjoint<T>(g, fields[j], csum(j), gin, gout, gC, rho, eps, p, flag, s));
+      HIPCHK(launch_step_adjoint<T>(g, fields[j], j == len - 1 ? clast(seg) : csum(j), gin, gout, gC, rho, eps,
+                                    p, flag, s));
       std::swap(gin, gout);
     }
   }

@@ -7,7 +7,7 @@
 namespace mcg {
 
 // CS = 1: also store the staple sums Cp (and Cr, OI) of every link in Cst, as two link fields
-// [Cp | Cr]; CS = 2: store them only (no smeared link), for the adjoint's first pass
+// [Cp | Cr], for the adjoint's first pass
 template <typename T, bool OI, int CS = 0>
 __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__ U,
                                                V2<T> *__restrict__ out, T rho, T wp, T wr,
@@ -28,7 +28,6 @@ __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__
     Links<T>{Cst, g.Vh}.store(mu, par, h, Cp);
     if (OI) Links<T>{Cst + (size_t)72 * g.Vh, g.Vh}.store(mu, par, h, Cr);
   }
-  if constexpr (CS == 2) return;
   M3<T> C;
 #pragma unroll
   for (int k = 0; k < 9; k++) {
