@@ -112,8 +112,11 @@ def test_c4_checkpointing_is_bitwise_and_fp32_error(S, env, c4):
     api, g, torch = env
     L, U64, U, G = c4
     a = api.smear_mcg_backward(U, 0.06, -0.25, 20, G, 1)
-    b = api.smear_mcg_backward(U, 0.06, -0.25, 20, G, 5)
-    assert torch.equal(a[0].data, b[0].data) and a[1:] == b[1:]
+    # every interval gives the bits of checkpointing each step: one that divides n, one whose last
+    # segment is shorter (7, 7, 6), and one segment (20; 0 means n)
+    for ck in (5, 7, 20, 0):
+        b = api.smear_mcg_backward(U, 0.06, -0.25, 20, G, ck)
+        assert torch.equal(a[0].data, b[0].data) and a[1:] == b[1:], ck
     # FP32 forward and adjoint against the FP64 adjoint (stated, loosely bounded)
     c = api.smear_mcg_backward(api.to_links(U64, 1), 0.06, -0.25, 20, G, 5)
     ga, gc = g.host_links(a[0]), g.host_links(c[0])
