@@ -443,7 +443,10 @@ mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, cons
  * checkpointed every ckpt_every steps and recomputed between checkpoints.
  * Device workspace held by the context: with c = ckpt_every (n if <= 0 or
  * > n) and m = (eps == 1 ? 1 : 2), ceil(n/c) * (1 + m) + (c - 1) * (1 + m) + 5
- * fields of U's size (the checkpoints, one segment's fields, and staple sums). */
+ * fields of U's size (the checkpoints, one segment's fields, and staple sums);
+ * if that cannot be allocated (or exceeds MCG_OPT_SCRATCH_LIMIT_MIB), ceil(n/c)
+ * + (c - 1) + 5 fields, the staples then formed again in the adjoint (the same
+ * results, more time). */
 mcg_status mcg_smear_mcg_backward(mcg_ctx *ctx, const mcg_field *U, double rho, double eps,
                                   int32_t n, const mcg_gauge *Gstar, int32_t ckpt_every,
                                   mcg_field *gradU, double *loss, double *dRho, double *dEps,

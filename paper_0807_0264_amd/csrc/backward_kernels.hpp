@@ -83,9 +83,10 @@ __global__ __launch_bounds__(256) void k_loss_seed(Geom g, const V2<T> *__restri
 // sums are stored by (direction and parity, tile), so their summation order does not depend on the
 // mapping.
 // --------------------------------------------------------------- pass A
-// Cst: the staple sums Cp (and Cr, OI) of U, stored by the smearing kernel (its CS modes), so that
-// the pass reads them instead of forming the staples again.
-template <typename T, bool OI>
+// STORED: Cst holds the staple sums Cp (and Cr, OI) of U, stored by the smearing kernel, and the
+// pass reads them; otherwise it forms the staples itself (when the workspace for the sums does not
+// fit).
+template <typename T, bool OI, bool STORED>
 __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ Cst,
                                                     const V2<T> *__restrict__ gOut, V2<T> *__restrict__ gU,
@@ -98,9 +99,15 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
   double drho = 0.0, deps = 0.0;
   if (h < g.Vh) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
-    const M3<T> Cp = Links<T>{const_cast<V2<T> *>(Cst), g.Vh}.load(mu, par, h);
-    const M3<T> Cr = OI ? Links<T>{const_cast<V2<T> *>(Cst) + (size_t)72 * g.Vh, g.Vh}.load(mu, par, h)
-                        : m_zero<T>();
+    M3<T> Cp, Cr;
+    if constexpr (STORED) {
+      Cp = Links<T>{const_cast<V2<T> *>(Cst), g.Vh}.load(mu, par, h);
+      Cr = OI ? Links<T>{const_cast<V2<T> *>(Cst) + (size_t)72 * g.Vh, g.Vh}.load(mu, par, h) : m_zero<T>();
+    } else {
+      int c[4];
+      coords_of(g, par, h, c);
+      staples<T, OI>(g, L, c, mu, Cp, Cr);
+    }
     // only C and dC/deps stay live through the adjoint of the exponential (C = rho Cu)
     M3<T> C, dC;
 #pragma unroll

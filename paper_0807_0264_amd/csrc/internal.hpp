@@ -131,7 +131,7 @@ int adjoint_blocks(const Geom &g);
 template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
                             hipStream_t s);
-// Cst: the staple sums of U as launch_smear_step stores them
+// Cst: the staple sums of U as launch_smear_step stores them, or null (the first pass forms them)
 template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
                                double rho, double eps, double *part, int *flag, hipStream_t s);

@@ -18,19 +18,20 @@ hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void 
 template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
                                double rho, double eps, double *part, int *flag, hipStream_t s) {
-  if (!Cst) return hipErrorInvalidValue;
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
   const int grid = 8 * ((g.Vh + 127) / 128);
   const int nb = grid;
   if (eps == 1.0) {
-    k_step_adj_a<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)Cst, (const V2<T> *)gOut,
-                                                (V2<T> *)gU, (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
+#define MCG_ADJ_A(OI, ST)                                                                                    \
+  k_step_adj_a<T, OI, ST><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)Cst, (const V2<T> *)gOut,   \
+                                               (V2<T> *)gU, (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag)
+    if (Cst) MCG_ADJ_A(false, true); else MCG_ADJ_A(false, false);
     k_eps_rect<T><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (T)rho, part + 2 * nb);
     k_step_adj_b<T, false><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
                                                 (T)wp, (T)wr);
   } else {
-    k_step_adj_a<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)Cst, (const V2<T> *)gOut,
-                                               (V2<T> *)gU, (V2<T> *)gC, (T)rho, (T)wp, (T)wr, part, flag);
+    if (Cst) MCG_ADJ_A(true, true); else MCG_ADJ_A(true, false);
+#undef MCG_ADJ_A
     k_step_adj_b<T, true><<<grid, 128, 0, s>>>(g, (const V2<T> *)U, (const V2<T> *)gC, (V2<T> *)gU, (T)rho,
                                                (T)wp, (T)wr);
   }

@@ -701,11 +701,21 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   const int nck = n > 0 ? (n + c - 1) / c : 0;
   // fields: nck checkpoints, c-1 segment slots, 2 forward temporaries, 2 gradients, grad_C, the
   // staple sums (Cp, and Cr for eps != 1) of the first c-1 steps of a segment, and those of every
-  // segment's last step, which the forward pass stores
+  // segment's last step, which the forward pass stores.  If that does not fit, the sums are not
+  // kept and the adjoint's first pass forms the staples itself (the same results, more time).
   const int ncs = eps == 1.0 ? 1 : 2;
-  const size_t nfields = (size_t)nck + (size_t)(c - 1) + 5 + (size_t)(c - 1) * ncs + (size_t)nck * ncs;
+  const size_t nbase = (size_t)nck + (size_t)(c - 1) + 5;
+  const size_t nfields = nbase + (size_t)(c - 1) * ncs + (size_t)nck * ncs;
   mcg_status st;
-  if ((st = ensure(ctx, ctx->ckpt, fb * nfields))) return st;
+  bool stored = true;
+  {
+    const std::string err = ctx->err;
+    if (ensure(ctx, ctx->ckpt, fb * nfields) != MCG_OK) {
+      ctx->err = err;
+      stored = false;
+      if ((st = ensure(ctx, ctx->ckpt, fb * nbase))) return st;
+    }
+  }
   const int nb_seed = field_blocks256(g), nb_step = adjoint_blocks(g);
   const size_t nparts = (size_t)nb_seed + (size_t)std::max(n, 1) * 3 * nb_step;
   if ((st = ensure(ctx, ctx->bw_part, sizeof(double) * nparts + 64))) return st;
@@ -713,8 +723,12 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   auto slot = [&](size_t i) { return (void *)(base + i * fb); };
   void *tmp0 = slot(nck + c - 1), *tmp1 = slot(nck + c), *gA = slot(nck + c + 1), *gB = slot(nck + c + 2),
        *gC = slot(nck + c + 3);
-  auto csum = [&](int j) { return slot((size_t)nck + c + 4 + (size_t)j * ncs); };  // step j < c-1 of a segment
-  auto clast = [&](int seg) { return slot((size_t)nck + c + 4 + (size_t)(c - 1) * ncs + (size_t)seg * ncs); };
+  auto csum = [&](int j) -> void * {  // step j < c-1 of a segment
+    return stored ? slot((size_t)nck + c + 4 + (size_t)j * ncs) : nullptr;
+  };
+  auto clast = [&](int seg) -> void * {  // a segment's last step
+    return stored ? slot((size_t)nck + c + 4 + (size_t)(c - 1) * ncs + (size_t)seg * ncs) : nullptr;
+  };
   double *part = (double *)ctx->bw_part.p;
   int *flag = (int *)(part + nparts);
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));

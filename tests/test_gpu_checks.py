@@ -137,6 +137,51 @@ def test_ring_falls_back_under_the_scratch_limit(S, g):
             assert lib.mcg_destroy(c) == A.MCG_OK
 
 
+def test_backward_falls_back_under_the_scratch_limit(S, g):
+    """A scratch limit that admits the backward's checkpoints and segment fields but not the staple
+    sums it keeps for the adjoint: the adjoint forms the staples itself, and the gradient and the
+    scalars equal those of a context without a limit (the same staple arithmetic in either kernel),
+    with no error left behind."""
+    import ctypes as C
+
+    import torch
+    from paper_0807_0264_amd import _abi as A
+    from paper_0807_0264_amd import api
+    lib = A.load()
+    L = (8, 8, 8, 8)
+    U = api.to_links(S.heatbath_field_gpu(L, S.sub_seed(77, 0), 5.7, 20), 1)
+    Gs = api.gauge_identity(L)
+
+    def run(ctx):
+        grad = api.empty_links(L, 1, torch.cuda.current_device())
+        fu, gg, fg = U.abi(), Gs.abi(), grad.abi()
+        loss, dr, de = C.c_double(), C.c_double(), C.c_double()
+        st = lib.mcg_smear_mcg_backward(ctx, C.byref(fu), 0.06, -0.25, 6, C.byref(gg), 3, C.byref(fg),
+                                        C.byref(loss), C.byref(dr), C.byref(de), api._stream())
+        torch.cuda.synchronize()
+        return st, g.host_links(grad), (loss.value, dr.value, de.value)
+
+    ctxs = [C.c_void_p(), C.c_void_p()]
+    for c in ctxs:
+        assert lib.mcg_create(C.byref(c), torch.cuda.current_device()) == A.MCG_OK
+    try:
+        # a field is 1.18 MB: 9 of them (2 checkpoints, 2 segment fields, 5 temporaries) fit in 16 MiB,
+        # the 17 with the staple sums do not
+        assert lib.mcg_set_option(ctxs[0], A.MCG_OPT_SCRATCH_LIMIT_MIB, 16) == A.MCG_OK
+        st, ga, sa = run(ctxs[0])
+        assert st == A.MCG_OK and lib.mcg_last_error(ctxs[0]) == b""
+        st, gb, sb = run(ctxs[1])
+        assert st == A.MCG_OK
+        rel = np.abs(ga - gb).max() / np.abs(gb).max()
+        print(f"fallback vs stored staple sums: max rel {rel:.2e}, bitwise {np.array_equal(ga, gb)}")
+        assert rel <= 1e-6
+        for x, y in zip(sa, sb):
+            assert abs(x - y) <= 1e-6 * abs(y)
+    finally:
+        for c in ctxs:
+            assert lib.mcg_destroy(c) == A.MCG_OK
+
+
 def test_destroy_returns_device_memory(S, g):
     """A context that ran an FP32 fix (working field, transform, transform
     ring, partial sums) and the batched tuner gives all of its device memory
