@@ -287,10 +287,7 @@ template <typename T> __device__ __forceinline__ void add_dag(T w, const M3<T> &
 __device__ __forceinline__ void opaque_start(const int in[4], int out[4]) {
 #pragma unroll
   for (int q = 0; q < 4; q++) out[q] = in[q];
-#if defined(__HIP_DEVICE_COMPILE__)
-#pragma unroll
-  for (int q = 0; q < 4; q++) __asm__ volatile("" : "+v"(out[q]));
-#endif
+  opaque_coords(out);
 }
 
 // The loops of one direction nu and sign SG through U_lam(y), added to acc with their weights.

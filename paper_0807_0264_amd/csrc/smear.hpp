@@ -116,13 +116,6 @@ template <typename T> __device__ __forceinline__ M3<T> exp_su3(const M3<T> &A) {
   return E;
 }
 
-// Plaquette part Cp and rectangle part Cr (OI only) of the staple sum of
-// link (c, mu): paths from x to x+mu.  Per nu != mu and per sign of nu: the
-// plaquette staple and the rectangles 2x1 ahead, 2x1 behind (long in mu) and
-// 1x2 (long in nu).  Rectangles that end on the same link share the last
-// product: the 2x1-behind and 1x2 paths of one nu and sign both end on the
-// link into x+mu along nu, and every 2x1-ahead path ends on U_mu(x+mu)^dag, so
-// their prefixes are summed first and multiplied by that link once.
 // Make the compiler treat coordinates as freshly produced (see staples).
 __device__ __forceinline__ void opaque_coords(int c[4]) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -133,6 +126,13 @@ __device__ __forceinline__ void opaque_coords(int c[4]) {
 #endif
 }
 
+// Plaquette part Cp and rectangle part Cr (OI only) of the staple sum of
+// link (c, mu): paths from x to x+mu.  Per nu != mu and per sign of nu: the
+// plaquette staple and the rectangles 2x1 ahead, 2x1 behind (long in mu) and
+// 1x2 (long in nu).  Rectangles that end on the same link share the last
+// product: the 2x1-behind and 1x2 paths of one nu and sign both end on the
+// link into x+mu along nu, and every 2x1-ahead path ends on U_mu(x+mu)^dag, so
+// their prefixes are summed first and multiplied by that link once.
 template <typename T, bool OI>
 __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const int c[4], int mu,
                                         M3<T> &Cp, M3<T> &Cr) {
