@@ -182,7 +182,8 @@ def scenario_planted():
 def scenario_backward(L, prec):
     U = rounded(field(L, 2040), prec)
     G = S.haar_gauge(L, S.sub_seed(2041))
-    for rho, eps, n, ck in ((0.1, 1.0, 3, 2), (0.06, -0.25, 3, 1), (0.06, -0.25, 2, 0), (0.06, -0.25, 5, 2)):
+    for rho, eps, n, ck in ((0.1, 1.0, 3, 2), (0.06, -0.25, 3, 1), (0.06, -0.25, 2, 0), (0.06, -0.25, 5, 2),
+                            (0.06, -0.25, 1, 0)):
         gd, loss, dr, de = E.smear_mcg_backward(E.links(U, prec), rho, eps, n, E.gauge(G), ck)
         go, dro, deo, losso = O.smear_loss_grad(U, rho, eps, n, G, ckpt_every=ck)
         tol = 1e-12 if prec == 0 else 1e-5
