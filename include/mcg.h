@@ -263,9 +263,11 @@ mcg_status mcg_autotune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, int32
  * now; every schedule -- tile order (MCG_OPT_ORDER 0/1/2) x paired sweeps
  * (MCG_OPT_PAIRED: 0/1 for FP32 with the ring, 0/2 for FP64 in the two-row
  * form, else 0) x slabs (MCG_OPT_SLABS 1/2/4) -- under the best variant;
- * every variant under the best schedule.  Each stage runs three interleaved
- * passes of 4 timed sweeps per point (after one untimed) and ranks points by
- * their median.  The choice is kept in the context for this batch shape
+ * every variant under the best schedule, together with the schedule in use
+ * before tuning.  Each stage runs three interleaved passes of 4 timed sweeps
+ * per point (after one untimed) and ranks points by their median; the last
+ * stage keeps the schedule in use unless a point is more than 1 % faster
+ * than it in the same passes.  The choice is kept in the context for this batch shape
  * (precision, storage form, transform ring, update variant and the fields'
  * extents in order) and used by mcg_fix and mcg_fix_batch on batches of that
  * shape instead of the context's variant and schedule options, until
@@ -281,7 +283,7 @@ typedef struct {
   int32_t paired;      /* MCG_OPT_PAIRED value */
   int32_t slabs;       /* MCG_OPT_SLABS value */
   double ms_per_sweep; /* median over the three passes, one sweep over the batch */
-  double ms_default;   /* the same for the variant and schedule in use before tuning */
+  double ms_default;   /* the same, in the same passes, for the schedule in use before tuning */
 } mcg_tune_choice;
 mcg_status mcg_tune_batch(mcg_ctx *ctx, int32_t B, const mcg_field *U, mcg_tune_choice *best,
                           void *stream);

@@ -1386,7 +1386,6 @@ static mcg_status tune_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_tune_ch
   mcg_status rc = MCG_OK;
   for (int v = 0; v < NUM_VARIANTS; v++) pts.push_back(Sched{v, base.order, base.paired, base.nslab});
   if (!(rc = stage(pts, med))) {
-    const double t_cur = med[base.variant];
     const int v1 = argmin(med);
     pts.clear();
     for (int o = 0; o <= 2; o++)
@@ -1396,8 +1395,20 @@ static mcg_status tune_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_tune_ch
       const Sched sb = pts[argmin(med)];
       pts.clear();
       for (int v = 0; v < NUM_VARIANTS; v++) pts.push_back(Sched{v, sb.order, sb.paired, sb.nslab});
+      // the schedule the batch would run untuned, timed in the same passes as the candidates, is
+      // kept unless one of them is more than 1 % faster (the rest is timing noise)
+      int ib = -1;
+      for (size_t i = 0; i < pts.size(); i++)
+        if (pts[i].variant == base.variant && pts[i].order == base.order && pts[i].paired == base.paired &&
+            pts[i].nslab == base.nslab)
+          ib = (int)i;
+      if (ib < 0) {
+        ib = (int)pts.size();
+        pts.push_back(base);
+      }
       if (!(rc = stage(pts, med))) {
-        const int i = argmin(med);
+        int i = argmin(med);
+        if (!(med[i] < 0.99 * med[ib])) i = ib;
         mcg_tune_choice c;
         memset(&c, 0, sizeof c);
         c.variant = pts[i].variant;
@@ -1405,7 +1416,7 @@ static mcg_status tune_impl(mcg_ctx *ctx, int B, const mcg_field *U, mcg_tune_ch
         c.paired = pts[i].paired;
         c.slabs = pts[i].nslab;
         c.ms_per_sweep = med[i];
-        c.ms_default = t_cur;
+        c.ms_default = med[ib];
         ctx->tuned[tune_key(ctx, B, U)] = c;
         if (out) *out = c;
       }
