@@ -95,7 +95,8 @@ hipError_t noalloc_scratch(int device, double **out) {
 namespace {
 
 // A ROCTX range around one call of the ABI (smear, fix, fix_batch, projection, counting, backward,
-// Wilson loops), so that a trace groups the kernels of a call under its name.
+// Wilson loops), and nested ones around the phases of the batched pipeline and the backward, so
+// that a trace groups the kernels of a call under its name.
 struct Range {
   explicit Range(const char *name) { roctxRangePushA(name); }
   ~Range() { roctxRangePop(); }
@@ -627,7 +628,10 @@ static mcg_status precondition_impl(mcg_ctx *ctx, int B, const mcg_field *U, dou
   for (int b = 0; b < B; b++) maxbytes = std::max(maxbytes, field_bytes(U[b].d, U[b].prec));
   if ((int)ctx->smeared.size() < B) ctx->smeared.resize(B);
   std::vector<mcg_field> S(U, U + B);
+  // ROCTX ranges mark each phase on the host: the fixes synchronise on their stop flags, so their
+  // ranges follow the device; the smearing steps are only queued within theirs
   if (n > 0) {
+    const Range range_("smear");
     for (int b = 0; b < B; b++) {
       if ((st = ensure(ctx, ctx->smeared[b], field_bytes(U[b].d, U[b].prec)))) return st;
       S[b].ptr = ctx->smeared[b].p;
@@ -644,11 +648,19 @@ static mcg_status precondition_impl(mcg_ctx *ctx, int B, const mcg_field *U, dou
     }
   }
   std::vector<mcg_fix_result> rs(B), rf(B);
-  const mcg_status s1 = fix_impl<T>(ctx, B, S.data(), G, opts, rs.data(), s, true);
+  mcg_status s1, s2;
+  {
+    const Range range_("fix smeared fields");
+    s1 = fix_impl<T>(ctx, B, S.data(), G, opts, rs.data(), s, true);
+  }
   if (s1 < 0) return s1;
-  const mcg_status s2 = fix_impl<T>(ctx, B, U, G, opts, rf.data(), s, true);
+  {
+    const Range range_("fix carried back");
+    s2 = fix_impl<T>(ctx, B, U, G, opts, rf.data(), s, true);
+  }
   if (s2 < 0) return s2;
   // every field's projection and count, then one copy back
+  const Range range_("project and count");
   std::vector<size_t> p0(B + 1, 0);
   for (int b = 0; b < B; b++) p0[b + 1] = p0[b] + (size_t)field_blocks256(geom_of(U[b].d));
   if ((st = ensure(ctx, ctx->pc_part, sizeof(double) * (p0[B] + B))) ||
@@ -736,15 +748,19 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
 
   // forward, keeping every c-th field and the staple sums of each segment's last step
   const void *cur = U->ptr;
-  for (int k = 0; k < n; k++) {
-    if (k % c == 0) HIPCHK(hipMemcpyAsync(slot(k / c), cur, fb, hipMemcpyDeviceToDevice, s));
-    void *nxt = (cur == tmp0) ? tmp1 : tmp0;
-    const bool last = k % c == c - 1 || k == n - 1;
-    HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s, last ? clast(k / c) : nullptr));
-    cur = nxt;
+  {
+    const Range range_("backward: forward smearing");
+    for (int k = 0; k < n; k++) {
+      if (k % c == 0) HIPCHK(hipMemcpyAsync(slot(k / c), cur, fb, hipMemcpyDeviceToDevice, s));
+      void *nxt = (cur == tmp0) ? tmp1 : tmp0;
+      const bool last = k % c == c - 1 || k == n - 1;
+      HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s, last ? clast(k / c) : nullptr));
+      cur = nxt;
+    }
   }
   HIPCHK(launch_loss_seed<T>(g, cur, Gstar->ptr, gA, part, s));
   void *gin = gA, *gout = gB;
+  const Range range_("backward: adjoint segments");
   for (int seg = nck - 1; seg >= 0; seg--) {
     const int k0 = seg * c, len = std::min(c, n - k0);
     // the segment's fields again from its checkpoint, keeping the staple sums that each smearing
