@@ -239,6 +239,11 @@ template <bool DAG, typename T> __device__ __forceinline__ M3<T> mul_o(const M3<
   if constexpr (DAG) return mul_nd(a, b);
   else return mul(a, b);
 }
+// c += a b, or c += a b^dag
+template <bool DAG, typename T> __device__ __forceinline__ void mac_o(const M3<T> &a, const M3<T> &b, M3<T> &c) {
+  if constexpr (DAG) mac_nd(a, b, c);
+  else mac(a, b, c);
+}
 
 // Steps K .. KEND-1 (K >= 1) of loop S (sign SG), from pos (left at the position after them): load
 // f_K and Gam_K, advance the recurrence.  The sign is a template argument, so every dagger is known
@@ -265,7 +270,7 @@ __device__ __forceinline__ void loop_steps(const Geom &g, const LD &L, const Lin
       }
     } else {
       M3<T> a = mul_o<back>(A, f);
-      add_to(mul_o<back>(P, G), a);
+      mac_o<back>(P, G, a);
       A = a;
       if constexpr (K + 1 < Loop<S>::n) P = mul_o<back>(P, f);
     }

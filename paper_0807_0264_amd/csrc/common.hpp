@@ -70,36 +70,140 @@ template <typename To, typename From> __device__ __forceinline__ M3<To> m_cvt(co
   for (int k = 0; k < 9; k++) r.e[k] = cvt<To>(a.e[k]);
   return r;
 }
+// ----------------------------------------------- products in a fixed FMA order
+// Every 3x3 product is written as explicit fused multiply-adds in a fixed order: left to the
+// compiler, a complex product term becomes a multiply and an FMA and the three terms two more
+// adds (16 instructions per element instead of 12), and the contraction it picks can differ from
+// one kernel to the next in the last bit.  Written out, the same product gives the same bits
+// wherever it is inlined.
+template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return fmaf(a, b, c);
+  else return fma(a, b, c);
+}
+// a0 b0 + a1 b1 + a2 b2
+template <typename T>
+__device__ __forceinline__ cx<T> dot3_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = a0.re * b0.re, im = a0.re * b0.im;
+  re = fma_t(-a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(-a1.im, b1.im, re);
+  im = fma_t(a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(-a2.im, b2.im, re);
+  im = fma_t(a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+// a0 conj(b0) + a1 conj(b1) + a2 conj(b2)
+template <typename T>
+__device__ __forceinline__ cx<T> dot3c_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = a0.re * b0.re, im = -(a0.re * b0.im);
+  re = fma_t(a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(a1.im, b1.im, re);
+  im = fma_t(-a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(a2.im, b2.im, re);
+  im = fma_t(-a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+// conj(a0) b0 + conj(a1) b1 + conj(a2) b2
+template <typename T>
+__device__ __forceinline__ cx<T> dot3n_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = a0.re * b0.re, im = a0.re * b0.im;
+  re = fma_t(a0.im, b0.im, re);
+  im = fma_t(-a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(a1.im, b1.im, re);
+  im = fma_t(a1.re, b1.im, im);
+  im = fma_t(-a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(a2.im, b2.im, re);
+  im = fma_t(a2.re, b2.im, im);
+  im = fma_t(-a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
 // a b
 template <typename T> __device__ __forceinline__ M3<T> mul(const M3<T> &a, const M3<T> &b) {
   M3<T> c;
 #pragma unroll
-  for (int i = 0; i < 3; i++)
+  for (int r = 0; r < 3; r++)
 #pragma unroll
-    for (int j = 0; j < 3; j++)
-      c.e[3 * i + j] = a.e[3 * i] * b.e[j] + a.e[3 * i + 1] * b.e[3 + j] + a.e[3 * i + 2] * b.e[6 + j];
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3_fma(a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
   return c;
 }
 // a b^dagger
 template <typename T> __device__ __forceinline__ M3<T> mul_nd(const M3<T> &a, const M3<T> &b) {
   M3<T> c;
 #pragma unroll
-  for (int i = 0; i < 3; i++)
+  for (int r = 0; r < 3; r++)
 #pragma unroll
-    for (int j = 0; j < 3; j++)
-      c.e[3 * i + j] = mulc(a.e[3 * i], b.e[3 * j]) + mulc(a.e[3 * i + 1], b.e[3 * j + 1]) +
-                       mulc(a.e[3 * i + 2], b.e[3 * j + 2]);
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3c_fma(a.e[3 * r], b.e[3 * q], a.e[3 * r + 1], b.e[3 * q + 1], a.e[3 * r + 2], b.e[3 * q + 2]);
   return c;
 }
 // a^dagger b
 template <typename T> __device__ __forceinline__ M3<T> mul_dn(const M3<T> &a, const M3<T> &b) {
   M3<T> c;
 #pragma unroll
-  for (int i = 0; i < 3; i++)
+  for (int r = 0; r < 3; r++)
 #pragma unroll
-    for (int j = 0; j < 3; j++)
-      c.e[3 * i + j] = cmul(a.e[i], b.e[j]) + cmul(a.e[3 + i], b.e[3 + j]) + cmul(a.e[6 + i], b.e[6 + j]);
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3n_fma(a.e[r], b.e[q], a.e[3 + r], b.e[3 + q], a.e[6 + r], b.e[6 + q]);
   return c;
+}
+// c += a b and c += a b^dagger, each element's FMA chain starting from c
+template <typename T>
+__device__ __forceinline__ cx<T> dot3_acc(cx<T> c, cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = fma_t(a0.re, b0.re, c.re), im = fma_t(a0.re, b0.im, c.im);
+  re = fma_t(-a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(-a1.im, b1.im, re);
+  im = fma_t(a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(-a2.im, b2.im, re);
+  im = fma_t(a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> dot3c_acc(cx<T> c, cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
+  T re = fma_t(a0.re, b0.re, c.re), im = fma_t(-a0.re, b0.im, c.im);
+  re = fma_t(a0.im, b0.im, re);
+  im = fma_t(a0.im, b0.re, im);
+  re = fma_t(a1.re, b1.re, re);
+  re = fma_t(a1.im, b1.im, re);
+  im = fma_t(-a1.re, b1.im, im);
+  im = fma_t(a1.im, b1.re, im);
+  re = fma_t(a2.re, b2.re, re);
+  re = fma_t(a2.im, b2.im, re);
+  im = fma_t(-a2.re, b2.im, im);
+  im = fma_t(a2.im, b2.re, im);
+  return cx<T>{re, im};
+}
+template <typename T> __device__ __forceinline__ void mac(const M3<T> &a, const M3<T> &b, M3<T> &c) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] =
+          dot3_acc(c.e[3 * r + q], a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
+}
+template <typename T> __device__ __forceinline__ void mac_nd(const M3<T> &a, const M3<T> &b, M3<T> &c) {
+#pragma unroll
+  for (int r = 0; r < 3; r++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      c.e[3 * r + q] = dot3c_acc(c.e[3 * r + q], a.e[3 * r], b.e[3 * q], a.e[3 * r + 1], b.e[3 * q + 1],
+                                 a.e[3 * r + 2], b.e[3 * q + 2]);
 }
 template <typename T> __device__ __forceinline__ M3<T> dag(const M3<T> &a) {
   M3<T> c;
@@ -408,68 +512,7 @@ template <typename T> struct Links12 {
   }
 };
 
-// ----------------------------------------- products in a fixed FMA order
-// G <- g G, the link updates of the half-sweep and the two-row reconstruction,
-// written with explicit fused multiply-adds in a fixed order: the compiler
-// contracts plain products into FMAs as it sees fit in each kernel, so two
-// kernels doing "the same" product can differ in the last bit; these give the
-// same bits wherever they are inlined.
-template <typename T> __device__ __forceinline__ T fma_t(T a, T b, T c) {
-  if constexpr (sizeof(T) == 4) return fmaf(a, b, c);
-  else return fma(a, b, c);
-}
-// a0 b0 + a1 b1 + a2 b2
-template <typename T>
-__device__ __forceinline__ cx<T> dot3_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
-  T re = a0.re * b0.re, im = a0.re * b0.im;
-  re = fma_t(-a0.im, b0.im, re);
-  im = fma_t(a0.im, b0.re, im);
-  re = fma_t(a1.re, b1.re, re);
-  re = fma_t(-a1.im, b1.im, re);
-  im = fma_t(a1.re, b1.im, im);
-  im = fma_t(a1.im, b1.re, im);
-  re = fma_t(a2.re, b2.re, re);
-  re = fma_t(-a2.im, b2.im, re);
-  im = fma_t(a2.re, b2.im, im);
-  im = fma_t(a2.im, b2.re, im);
-  return cx<T>{re, im};
-}
-// a0 conj(b0) + a1 conj(b1) + a2 conj(b2)
-template <typename T>
-__device__ __forceinline__ cx<T> dot3c_fma(cx<T> a0, cx<T> b0, cx<T> a1, cx<T> b1, cx<T> a2, cx<T> b2) {
-  T re = a0.re * b0.re, im = -(a0.re * b0.im);
-  re = fma_t(a0.im, b0.im, re);
-  im = fma_t(a0.im, b0.re, im);
-  re = fma_t(a1.re, b1.re, re);
-  re = fma_t(a1.im, b1.im, re);
-  im = fma_t(-a1.re, b1.im, im);
-  im = fma_t(a1.im, b1.re, im);
-  re = fma_t(a2.re, b2.re, re);
-  re = fma_t(a2.im, b2.im, re);
-  im = fma_t(-a2.re, b2.im, im);
-  im = fma_t(a2.im, b2.re, im);
-  return cx<T>{re, im};
-}
-// a b
-template <typename T> __device__ __forceinline__ M3<T> mul_fixed(const M3<T> &a, const M3<T> &b) {
-  M3<T> c;
-#pragma unroll
-  for (int r = 0; r < 3; r++)
-#pragma unroll
-    for (int q = 0; q < 3; q++)
-      c.e[3 * r + q] = dot3_fma(a.e[3 * r], b.e[q], a.e[3 * r + 1], b.e[3 + q], a.e[3 * r + 2], b.e[6 + q]);
-  return c;
-}
-// a b^dagger
-template <typename T> __device__ __forceinline__ M3<T> mul_nd_fixed(const M3<T> &a, const M3<T> &b) {
-  M3<T> c;
-#pragma unroll
-  for (int r = 0; r < 3; r++)
-#pragma unroll
-    for (int q = 0; q < 3; q++)
-      c.e[3 * r + q] = dot3c_fma(a.e[3 * r], b.e[3 * q], a.e[3 * r + 1], b.e[3 * q + 1], a.e[3 * r + 2], b.e[3 * q + 2]);
-  return c;
-}
+// ----------------------------------------- products of rows in the fixed FMA order
 // rows 0 and 1 of a b and of a b^dagger (row 2 zero); the first needs all of b, the second only
 // rows 0 and 1 of a
 template <typename T> __device__ __forceinline__ M3<T> mul_fixed_rows(const M3<T> &a, const M3<T> &b) {

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
           M3<T> f = F[mu];
           opaque_rows(f);
           third_row_fixed(f);
-          const M3<T> fn = mul_fixed(gr, f);
+          const M3<T> fn = mul(gr, f);
           W.store_off(mu, of, fn);
           if (WR) r += tr2(fn);
         }
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
           M3<T> bk = Bk[mu];
           opaque_rows(bk);
           third_row_fixed(bk);
-          const M3<T> bn = mul_nd_fixed(bk, gr);
+          const M3<T> bn = mul_nd(bk, gr);
           W.store_off(mu, ob[mu], bn);
           if (WR) r += tr2(bn);
         }
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(BS, OCC) void k_halfsweep(const LatDesc<T> *__restr
       // FP32 g: row 2 rebuilt in FP64 from rows 0 and 1; the same fixed arithmetic as k_fold, so
       // that updating G here and folding the ring later give the same bits
       if constexpr (sizeof(T) == 4) third_row_fixed(gd);
-      G.store(par, h, mul_fixed(gd, G.load_fixed(par, h)));
+      G.store(par, h, mul(gd, G.load_fixed(par, h)));
     }
   }
   if (WR) {
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(BS) void k_fold(const LatDesc<T> *__restrict__ D, i
         gj.e[k] = cx<double>{(double)v.x, (double)v.y};
       }
       third_row_fixed(gj);
-      m = mul_fixed(gj, m);
+      m = mul(gj, m);
       if constexpr (C12) third_row_fixed(m);  // as a store and a reload of the two-row form would
     }
     G.store_stream(par, h, m);

@@ -160,7 +160,7 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
       const M3<T> umu_xpn = L.at(g, cpn, mu);   // U_mu(x+nu)
       const M3<T> unu_xpm = L.at(g, bpm, nu);   // U_nu(x+mu)
       const M3<T> up = mul(unu_x, umu_xpn);     // U_nu(x) U_mu(x+nu)
-      add_to(mul_nd(up, unu_xpm), Cp);
+      mac_nd(up, unu_xpm, Cp);
       if (OI) {
         int cpnpm[4], cp2m[4], cmmpn[4], cp2n[4];
         moved(g, cpn, mu, +1, cpnpm);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
         M3<T> t, end;
         // 2x1 ahead: U_nu(x) U_mu(x+nu) U_mu(x+nu+mu) U_nu(x+2mu)^dag [U_mu(x+mu)^dag]
         t = mul(up, L.at(g, cpnpm, mu));
-        add_to(mul_nd(t, L.at(g, cp2m, nu)), ahead);
+        mac_nd(t, L.at(g, cp2m, nu), ahead);
         // 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu) U_mu(x-mu+nu) U_mu(x+nu) [U_nu(x+mu)^dag]
         t = mul_dn(umu_xmm, L.at(g, bmm, nu));
         t = mul(t, L.at(g, cmmpn, mu));
@@ -178,8 +178,8 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
         // 1x2: U_nu(x) U_nu(x+nu) U_mu(x+2nu) U_nu(x+mu+nu)^dag [U_nu(x+mu)^dag]
         t = mul(unu_x, L.at(g, cpn, nu));
         t = mul(t, L.at(g, cp2n, mu));
-        add_to(mul_nd(t, L.at(g, cpnpm, nu)), end);
-        add_to(mul_nd(end, unu_xpm), Cr);
+        mac_nd(t, L.at(g, cpnpm, nu), end);
+        mac_nd(end, unu_xpm, Cr);
       }
     }
     {  // -nu
@@ -193,7 +193,7 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
       const M3<T> umu_xmn = L.at(g, cmn, mu);      // U_mu(x-nu)
       const M3<T> unu_xmnpm = L.at(g, cmnpm, nu);  // U_nu(x-nu+mu)
       const M3<T> dn = mul_dn(unu_xmn, umu_xmn);   // U_nu(x-nu)^dag U_mu(x-nu)
-      add_to(mul(dn, unu_xmnpm), Cp);
+      mac(dn, unu_xmnpm, Cp);
       if (OI) {
         int cmnp2m[4], cmmmn[4], cm2n[4], cm2npm[4];
         moved(g, cmnpm, mu, +1, cmnp2m);
@@ -203,7 +203,7 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
         M3<T> t, end;
         // 2x1 ahead: U_nu(x-nu)^dag U_mu(x-nu) U_mu(x-nu+mu) U_nu(x-nu+2mu) [U_mu(x+mu)^dag]
         t = mul(dn, L.at(g, cmnpm, mu));
-        add_to(mul(t, L.at(g, cmnp2m, nu)), ahead);
+        mac(t, L.at(g, cmnp2m, nu), ahead);
         // 2x1 behind: U_mu(x-mu)^dag U_nu(x-mu-nu)^dag U_mu(x-mu-nu) U_mu(x-nu) [U_nu(x-nu+mu)]
         t = dag(mul(L.at(g, cmmmn, nu), umu_xmm));
         t = mul(t, L.at(g, cmmmn, mu));
@@ -211,12 +211,12 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
         // 1x2: U_nu(x-nu)^dag U_nu(x-2nu)^dag U_mu(x-2nu) U_nu(x-2nu+mu) [U_nu(x-nu+mu)]
         t = dag(mul(L.at(g, cm2n, nu), unu_xmn));
         t = mul(t, L.at(g, cm2n, mu));
-        add_to(mul(t, L.at(g, cm2npm, nu)), end);
-        add_to(mul(end, unu_xmnpm), Cr);
+        mac(t, L.at(g, cm2npm, nu), end);
+        mac(end, unu_xmnpm, Cr);
       }
     }
   }
-  if (OI) add_to(mul_nd(ahead, L.at(g, cpm, mu)), Cr);  // ... U_mu(x+mu)^dag
+  if (OI) mac_nd(ahead, L.at(g, cpm, mu), Cr);  // ... U_mu(x+mu)^dag
 }
 
 }  // namespace mcg
