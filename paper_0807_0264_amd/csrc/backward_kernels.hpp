@@ -77,11 +77,11 @@ __global__ __launch_bounds__(256) void k_loss_seed(Geom g, const V2<T> *__restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// The adjoint kernels run one block per (tile, direction, parity): the eight blocks of a tile follow
-// each other and each XCD takes a contiguous range of tiles (xcd_range), so a site's neighbours
-// mostly share an XCD's L2 and the links of a tile are loaded while still cached; per-block partial
-// sums are stored by (direction and parity, tile), so their summation order does not depend on the
-// mapping.
+// The adjoint kernels run one block per (tile, direction, parity), the tiles as gather_site lays
+// them out: the eight blocks of a tile follow each other and each XCD takes a contiguous range of
+// tiles (xcd_range), so a site's neighbours mostly share an XCD's L2 and the links of a tile are
+// loaded while still cached; per-block partial sums are stored by (direction and parity, tile), so
+// their summation order does not depend on which XCD runs a block or when.
 // --------------------------------------------------------------- pass A
 // STORED: Cst holds the staple sums Cp (and Cr, OI) of U, stored by the smearing kernel, and the
 // pass reads them; otherwise it forms the staples itself (when the workspace for the sums does not
@@ -94,10 +94,10 @@ __global__ __launch_bounds__(128) void k_step_adj_a(Geom g, const V2<T> *__restr
                                                     int *flag) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x), nT = (int)gridDim.x >> 3;
   const int tile = w >> 3, row = w & 7;
-  const int h = tile * 128 + threadIdx.x;
+  const int h = gather_site(g, tile, (int)threadIdx.x);
   const int mu = row >> 1, par = row & 1;
   double drho = 0.0, deps = 0.0;
-  if (h < g.Vh) {
+  if (h >= 0) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
     M3<T> Cp, Cr;
     if constexpr (STORED) {
@@ -179,10 +179,10 @@ __global__ __launch_bounds__(128) void k_eps_rect(Geom g, const V2<T> *__restric
                                                   const V2<T> *__restrict__ gC, T rho, double *part) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x), nT = (int)gridDim.x >> 3;
   const int tile = w >> 3, row = w & 7;
-  const int h = tile * 128 + threadIdx.x;
+  const int h = gather_site(g, tile, (int)threadIdx.x);
   const int mu = row >> 1, par = row & 1;
   double deps = 0.0;
-  if (h < g.Vh) {
+  if (h >= 0) {
     const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
     int c[4];
     coords_of(g, par, h, c);
@@ -336,8 +336,8 @@ template <typename T, bool OI>
 __global__ __launch_bounds__(128) void k_step_adj_b(Geom g, const V2<T> *__restrict__ U,
                                                     const V2<T> *__restrict__ gC, V2<T> *gU, T rho, T wp, T wr) {
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
-  const int h = (w >> 3) * 128 + threadIdx.x;
-  if (h >= g.Vh) return;
+  const int h = gather_site(g, w >> 3, (int)threadIdx.x);
+  if (h < 0) return;
   const int lam = (w & 7) >> 1, par = w & 1;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
   const Links<T> GC{const_cast<V2<T> *>(gC), g.Vh}, GU{gU, g.Vh};

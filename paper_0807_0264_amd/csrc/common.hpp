@@ -310,6 +310,22 @@ __device__ __forceinline__ int xcd_range(int i, int n) {
   const int x = i & 7, q = n >> 3, r = n & 7;
   return x * q + (x < r ? x : r) + (i >> 3);
 }
+// Tiles of the gather kernels (smearing and its adjoint): a tile is 128 half-sites of one t-slice
+// (S = Vh / Lt half-sites per slice, ceil(S / 128) tiles each).  Tiles come in groups of up to
+// eight consecutive t-slices, and inside a group the slice index runs fastest, so the tiles that
+// hold a site's t-neighbours are a few tiles away, not a whole slice (at 32^3x64 a slice of links
+// is larger than an XCD's L2).  gather_site maps (tile, lane) to the half-site index, or -1 for the
+// idle lanes of a slice's last tile; a bijection of [0, gather_tiles) x [0, 128) onto the
+// half-sites and the idle lanes.
+__host__ __device__ inline int gather_tiles(const Geom &g) { return g.L[3] * ((g.Vh / g.L[3] + 127) / 128); }
+__device__ __forceinline__ int gather_site(const Geom &g, int tile, int lane) {
+  const int S = g.Vh / g.L[3], span = 8 * ((S + 127) / 128);
+  const int gi = tile / span, rem = tile - gi * span;
+  const int bt = g.L[3] - 8 * gi < 8 ? g.L[3] - 8 * gi : 8;
+  const int ch = rem / bt, t = 8 * gi + (rem - ch * bt);
+  const int s = ch * 128 + lane;
+  return s < S ? t * S + s : -1;
+}
 __device__ __forceinline__ int lex_index(const Geom &g, const int c[4]) {
   return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
 }

@@ -5,7 +5,7 @@
 
 namespace mcg {
 
-int adjoint_blocks(const Geom &g) { return 8 * ((g.Vh + 127) / 128); }
+int adjoint_blocks(const Geom &g) { return 8 * gather_tiles(g); }
 
 template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
@@ -19,7 +19,7 @@ template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
                                double rho, double eps, double *part, int *flag, hipStream_t s) {
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
-  const int grid = 8 * ((g.Vh + 127) / 128);
+  const int grid = adjoint_blocks(g);
   const int nb = grid;
   if (eps == 1.0) {
 #define MCG_ADJ_A(OI, ST)                                                                                    \

@@ -13,7 +13,7 @@ template <typename T>
 hipError_t launch_smear_step(const Geom &g, const void *U, void *out, double rho, double eps,
                              hipStream_t s, void *Cst) {
   const double wp = (5.0 - 2.0 * eps) / 3.0, wr = -(1.0 - eps) / 12.0;
-  const int grid = 8 * ((g.Vh + 127) / 128);
+  const int grid = 8 * gather_tiles(g);
   if (!out) return hipErrorInvalidValue;
   const V2<T> *u = (const V2<T> *)U;
   V2<T> *o = (V2<T> *)out, *cs = (V2<T> *)Cst;

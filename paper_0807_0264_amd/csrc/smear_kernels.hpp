@@ -12,12 +12,13 @@ template <typename T, bool OI, int CS = 0>
 __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__ U,
                                                V2<T> *__restrict__ out, T rho, T wp, T wr,
                                                V2<T> *__restrict__ Cst = nullptr) {
-  // one block per (tile, direction, parity); the eight blocks of a tile follow each other and each
-  // XCD takes a contiguous range of tiles (xcd_range), so the staple links that the eight share,
-  // and those of the next tiles along z and t, are still in that XCD's L2 or the last-level cache
+  // one block per (tile, direction, parity), the tiles as gather_site lays them out; the eight blocks
+  // of a tile follow each other and each XCD takes a contiguous range of tiles (xcd_range), so the
+  // staple links that the eight share, and those of the neighbouring tiles along z and t, are still
+  // in that XCD's L2
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
-  const int h = (w >> 3) * 128 + threadIdx.x;
-  if (h >= g.Vh) return;
+  const int h = gather_site(g, w >> 3, (int)threadIdx.x);
+  if (h < 0) return;
   const int mu = (w & 7) >> 1, par = w & 1;
   const Links<T> L{const_cast<V2<T> *>(U), g.Vh};
   int c[4];
