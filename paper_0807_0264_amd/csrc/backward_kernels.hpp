@@ -44,6 +44,49 @@ template <typename T> __device__ __forceinline__ cx<T> trdot(const M3<T> &a, con
   return s;
 }
 
+// ---------------------------------------------------------- partial sums
+// The loss and the two scalar derivatives from the per-block partials, laid out as the seed's
+// nb_seed block sums and then, for each of the n steps, 3 nb entries: the (dL/drho, dL/deps) pair
+// of each block, then the rectangle part of dL/deps of each block (zero where no kernel writes it).
+// Block q (0: loss, 1: dL/drho, 2: dL/deps) sums its terms in a fixed order: thread t adds the
+// terms t, t + 1024, ... of its sequence in turn (eight loads in flight), then block_sum, so the
+// results do not depend on the launch.
+template <class F> __device__ __forceinline__ double sum_sequence(F at, long long cnt) {
+  double s = 0.0;
+  long long i = threadIdx.x;
+  for (; i + 7 * 1024 < cnt; i += 8 * 1024) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = at(i + k * 1024);
+#pragma unroll
+    for (int k = 0; k < 8; k++) s += v[k];
+  }
+  for (; i < cnt; i += 1024) s += at(i);
+  return s;
+}
+__global__ __launch_bounds__(1024) void k_reduce_parts(const double *__restrict__ part, int nb_seed, int n, int nb,
+                                                       double *__restrict__ out) {
+  const int q = blockIdx.x;
+  const double *p = part + nb_seed;
+  const long long step = 3LL * nb;
+  double s;
+  if (q == 0) {
+    s = sum_sequence([&](long long i) { return part[i]; }, nb_seed);
+  } else if (q == 1) {
+    s = sum_sequence([&](long long i) { const long long k = i / nb; return p[k * step + 2 * (i - k * nb)]; },
+                     (long long)n * nb);
+  } else {
+    s = sum_sequence(
+        [&](long long i) {
+          const long long k = i / (2LL * nb), j = i - k * 2LL * nb;
+          return j < nb ? p[k * step + 2 * j + 1] : p[k * step + 2LL * nb + (j - nb)];
+        },
+        2LL * n * nb);
+  }
+  s = block_sum<1024>(s);
+  if (threadIdx.x == 0) out[q] = s;
+}
+
 // ------------------------------------------------------------------ seed
 // L = (1/(9 N_l)) sum |tr W|^2 with W = G(x) S G(x+mu)^dag;
 // grad_S = G(x)^dag (2c tr W) G(x+mu), c = 1/(9 N_l).

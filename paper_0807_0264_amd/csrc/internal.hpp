@@ -128,6 +128,10 @@ hipError_t launch_zero(double *p, int n, hipStream_t s);
 // nb = adjoint_blocks(g); *flag is set if an exponent lies outside the
 // range of the unscaled series.
 int adjoint_blocks(const Geom &g);
+// out[0..2] = the loss, dL/drho and dL/deps from the partials of launch_loss_seed (nb_seed block
+// sums) and of n launch_step_adjoint calls (3 nb entries each, as they lay them out), each summed in
+// a fixed order on the device
+hipError_t launch_reduce_parts(const double *part, int nb_seed, int n, int nb, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void *grad, double *part,
                             hipStream_t s);

@@ -15,6 +15,11 @@ hipError_t launch_loss_seed(const Geom &g, const void *S, const double *G, void 
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_parts(const double *part, int nb_seed, int n, int nb, double *out, hipStream_t s) {
+  k_reduce_parts<<<3, 1024, 0, s>>>(part, nb_seed, n, nb, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step_adjoint(const Geom &g, const void *U, const void *Cst, const void *gOut, void *gU, void *gC,
                                double rho, double eps, double *part, int *flag, hipStream_t s) {

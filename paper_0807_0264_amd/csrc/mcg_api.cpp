@@ -701,8 +701,8 @@ static mcg_status precondition_impl(mcg_ctx *ctx, int B, const mcg_field *U, dou
 // L = R(S_n(U)^G*): forward with a checkpoint every c steps, seed grad_S_n,
 // then per segment (last first) recompute the c fields from the checkpoint
 // and apply the step adjoints in reverse.  Partial sums of L, dL/drho and
-// dL/deps stay on the device until the end and are added on the host in a
-// fixed order.
+// dL/deps stay on the device and are reduced there at the end in a fixed
+// order; three scalars and a flag come back.
 template <typename T>
 mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double eps, int n, const mcg_gauge *Gstar,
                          int ckpt_every, mcg_field *gradU, double *loss, double *dRho, double *dEps,
@@ -742,7 +742,8 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
     return stored ? slot((size_t)nck + c + 4 + (size_t)(c - 1) * ncs + (size_t)seg * ncs) : nullptr;
   };
   double *part = (double *)ctx->bw_part.p;
-  int *flag = (int *)(part + nparts);
+  double *red = part + nparts;      // the three reduced scalars ...
+  int *flag = (int *)(red + 3);     // ... and the adjoint's range flag, copied back together
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(part, 0, sizeof(double) * nparts, s));
 
@@ -782,27 +783,18 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
     }
   }
   HIPCHK(hipMemcpyAsync(gradU->ptr, gin, fb, hipMemcpyDeviceToDevice, s));
-  std::vector<double> h(nparts);
-  int hflag = 0;
-  HIPCHK(hipMemcpyAsync(h.data(), part, sizeof(double) * nparts, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_reduce_parts(part, nb_seed, n, nb_step, red, s));
+  double h[4];
+  HIPCHK(hipMemcpyAsync(h, red, 3 * sizeof(double) + sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  int hflag;
+  std::memcpy(&hflag, &h[3], sizeof(int));
   if (hflag)
     return fail(ctx, MCG_EINPUT, "a smearing exponent exceeds the range of the adjoint's series "
                                  "(spectral radius of C U^dag above 4)");
-  double L = 0.0, dr = 0.0, de = 0.0;
-  for (int b = 0; b < nb_seed; b++) L += h[b];
-  for (int k = 0; k < n; k++) {
-    const double *p = h.data() + nb_seed + (size_t)k * 3 * nb_step;
-    for (int b = 0; b < nb_step; b++) {
-      dr += p[2 * b];
-      de += p[2 * b + 1];
-    }
-    for (int b = 0; b < nb_step; b++) de += p[2 * nb_step + b];
-  }
-  *loss = L / (9.0 * (double)(4 * g.V));
-  *dRho = dr;
-  *dEps = de;
+  *loss = h[0] / (9.0 * (double)(4 * g.V));
+  *dRho = h[1];
+  *dEps = h[2];
   return MCG_OK;
 }
 
