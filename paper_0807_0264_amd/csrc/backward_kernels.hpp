@@ -49,40 +49,42 @@ template <typename T> __device__ __forceinline__ cx<T> trdot(const M3<T> &a, con
 // nb_seed block sums and then, for each of the n steps, 3 nb entries: the (dL/drho, dL/deps) pair
 // of each block, then the rectangle part of dL/deps of each block (zero where no kernel writes it).
 // Block q (0: loss, 1: dL/drho, 2: dL/deps) sums its terms in a fixed order: thread t adds the
-// terms t, t + 1024, ... of its sequence in turn (eight loads in flight), then block_sum, so the
-// results do not depend on the launch.
-template <class F> __device__ __forceinline__ double sum_sequence(F at, long long cnt) {
+// terms t, t + 1024, ... of its sequence in turn (sixteen loads in flight), then block_sum, so the
+// results do not depend on the launch.  A sequence is n runs of len terms, run k starting at
+// base + k * 3 nb; term j of a run sits at offset off(j).
+template <class F>
+__device__ __forceinline__ double sum_runs(const double *base, int n, int len, long long nb3, F off) {
   double s = 0.0;
-  long long i = threadIdx.x;
-  for (; i + 7 * 1024 < cnt; i += 8 * 1024) {
-    double v[8];
+  int k = 0, j = threadIdx.x;  // this thread's next term: run k, index j
+  while (j >= len && k < n) j -= len, k++;
+  while (k < n) {
+    double v[16];
+    int m = 0;
 #pragma unroll
-    for (int k = 0; k < 8; k++) v[k] = at(i + k * 1024);
+    for (int u = 0; u < 16; u++) {
+      v[u] = 0.0;
+      if (k < n) {
+        v[u] = base[(long long)k * nb3 + off(j)];
+        m = u + 1;
+        j += 1024;
+        while (j >= len && k < n) j -= len, k++;
+      }
+    }
 #pragma unroll
-    for (int k = 0; k < 8; k++) s += v[k];
+    for (int u = 0; u < 16; u++)
+      if (u < m) s += v[u];
   }
-  for (; i < cnt; i += 1024) s += at(i);
   return s;
 }
 __global__ __launch_bounds__(1024) void k_reduce_parts(const double *__restrict__ part, int nb_seed, int n, int nb,
                                                        double *__restrict__ out) {
   const int q = blockIdx.x;
-  const double *p = part + nb_seed;
-  const long long step = 3LL * nb;
+  const long long nb3 = 3LL * nb;
   double s;
-  if (q == 0) {
-    s = sum_sequence([&](long long i) { return part[i]; }, nb_seed);
-  } else if (q == 1) {
-    s = sum_sequence([&](long long i) { const long long k = i / nb; return p[k * step + 2 * (i - k * nb)]; },
-                     (long long)n * nb);
-  } else {
-    s = sum_sequence(
-        [&](long long i) {
-          const long long k = i / (2LL * nb), j = i - k * 2LL * nb;
-          return j < nb ? p[k * step + 2 * j + 1] : p[k * step + 2LL * nb + (j - nb)];
-        },
-        2LL * n * nb);
-  }
+  if (q == 0) s = sum_runs(part, 1, nb_seed, 0, [](int j) { return (long long)j; });
+  else if (q == 1) s = sum_runs(part + nb_seed, n, nb, nb3, [](int j) { return 2LL * j; });
+  else
+    s = sum_runs(part + nb_seed, n, 2 * nb, nb3, [nb](int j) { return j < nb ? 2LL * j + 1 : (long long)nb + j; });
   s = block_sum<1024>(s);
   if (threadIdx.x == 0) out[q] = s;
 }

@@ -126,6 +126,17 @@ __device__ __forceinline__ void opaque_coords(int c[4]) {
 #endif
 }
 
+// Make the compiler treat a loaded matrix as produced here: every load into it is complete at this
+// point (see staples).
+template <typename T> __device__ __forceinline__ void opaque_m3(M3<T> &m) {
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+  for (int k = 0; k < 9; k++) __asm__ volatile("" : "+v"(m.e[k].re), "+v"(m.e[k].im));
+#else
+  (void)m;
+#endif
+}
+
 // Plaquette part Cp and rectangle part Cr (OI only) of the staple sum of
 // link (c, mu): paths from x to x+mu.  Per nu != mu and per sign of nu: the
 // plaquette staple and the rectangles 2x1 ahead, 2x1 behind (long in mu) and
@@ -143,6 +154,34 @@ __device__ __forceinline__ void staples(const Geom &g, const Links<T> &L, const 
   moved(g, c, mu, +1, cpm);
   moved(g, c, mu, -1, cmm);
   const M3<T> umu_xmm = OI ? L.at(g, cmm, mu) : m_zero<T>();  // U_mu(x-mu)
+  if constexpr (!OI) {
+    // Stout: the six links of a direction are loaded together and (FP32) held until all six are in,
+    // so a wave has six loads in flight instead of three; 142 VGPRs and three waves per SIMD
+    // instead of 94 and five, 1.7 % less time.  The sums are taken in the same order.
+    for (int nu = 0; nu < 4; nu++) {
+      if (nu == mu) continue;
+      int b[4] = {c[0], c[1], c[2], c[3]}, bpm[4] = {cpm[0], cpm[1], cpm[2], cpm[3]};
+      opaque_coords(b);
+      opaque_coords(bpm);
+      int cpn[4], cmn[4], cmnpm[4];
+      moved(g, b, nu, +1, cpn);
+      moved(g, b, nu, -1, cmn);
+      moved(g, cmn, mu, +1, cmnpm);
+      M3<T> unu_x = L.at(g, b, nu), umu_xpn = L.at(g, cpn, mu), unu_xpm = L.at(g, bpm, nu);  // +nu side
+      M3<T> unu_xmn = L.at(g, cmn, nu), umu_xmn = L.at(g, cmn, mu), unu_xmnpm = L.at(g, cmnpm, nu);  // -nu
+      if constexpr (sizeof(T) == 4) {
+        opaque_m3(unu_x);
+        opaque_m3(umu_xpn);
+        opaque_m3(unu_xpm);
+        opaque_m3(unu_xmn);
+        opaque_m3(umu_xmn);
+        opaque_m3(unu_xmnpm);
+      }
+      mac_nd(mul(unu_x, umu_xpn), unu_xpm, Cp);       // U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
+      mac(mul_dn(unu_xmn, umu_xmn), unu_xmnpm, Cp);  // U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)
+    }
+    return;
+  }
   for (int nu = 0; nu < 4; nu++) {
     if (nu == mu) continue;
     // Each side of the direction starts from opaque copies of the base coordinates, so the
