@@ -26,7 +26,7 @@ def _fd(f, h):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 8)])
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 4, 8), (12, 12, 10, 6)])
 @pytest.mark.parametrize("rho,eps,n,ck", [(0.1, 1.0, 3, 2), (0.06, -0.25, 3, 1)])
 def test_backward_vs_oracle(S, O, env, L, prec, rho, eps, n, ck):
     api, g, torch = env

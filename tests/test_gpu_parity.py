@@ -71,6 +71,23 @@ def test_smear(S, O, g, api, L, prec, eps):
     assert np.abs(got - want).max() < (1e-13 if prec == 0 else 1e-5)
 
 
+# t-slices of 720 and 500 half-sites: several 128-site tiles per slice with a ragged last one, and
+# 6 and 12 slices, so the last group of up to eight slices that the smearing kernel walks with the
+# slice index fastest is a short one
+RAGGED = [(12, 12, 10, 6), (10, 10, 10, 12)]
+
+
+@pytest.mark.parametrize("eps", [1.0, -0.25])
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", RAGGED)
+def test_smear_ragged_tiles(S, O, g, api, L, prec, eps):
+    U = g.rounded(field(S, L, 1006), prec)
+    rho = 0.1 if eps == 1.0 else 0.06
+    got = g.host_links(api.smear(g.links(U, prec), rho, eps, 3))
+    want = O.smear(U, rho, eps, 3)
+    assert np.abs(got - want).max() < (1e-13 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_smear_zero_steps_and_zero_rho(S, g, api, prec):
     L = (6, 4, 4, 8)
