@@ -355,25 +355,26 @@ __device__ __forceinline__ void loops_of(const Geom &g, const LD &L, const Links
       add_dag(wr, A, acc);
     }
   }
-  if constexpr (OI) {  // S3: L N N -L -N -N, from its own start (its first step is two loads)
-    int p3[4];
-    opaque_start(yl, p3);
-    loop_steps<T, 3, SG, 1, 6, LD>(g, L, GC, p3, lam, nu, A, P);
-    add_dag(wr, A, acc);
-  }
   int pos[4];
   opaque_start(yl, pos);
-  loop_steps<T, 0, SG, 1, 3, LD>(g, L, GC, pos, lam, nu, A, P);  // N, -L: shared by S0 and S2
-  {  // S0: L N -L -N; its last step leaves A and P as S2 continues from them
-    int p0[4] = {pos[0], pos[1], pos[2], pos[3]};
-    M3<T> A0 = A, P0 = P;
-    loop_steps<T, 0, SG, 3, 4, LD>(g, L, GC, p0, lam, nu, A0, P0);
-    add_dag(wp, A0, acc);
+  loop_steps<T, 0, SG, 1, 2, LD>(g, L, GC, pos, lam, nu, A, P);  // N, shared by S0, S2, S3
+  if constexpr (OI) {  // S3: L N N -L -N -N
+    int p3[4];
+    opaque_start(pos, p3);
+    M3<T> A3 = A, P3 = P;
+    loop_steps<T, 3, SG, 2, 6, LD>(g, L, GC, p3, lam, nu, A3, P3);
+    add_dag(wr, A3, acc);
   }
+  loop_steps<T, 0, SG, 2, 3, LD>(g, L, GC, pos, lam, nu, A, P);  // -L, shared by S0 and S2
   if constexpr (OI) {  // S2: L N -L -L -N L
-    loop_steps<T, 2, SG, 3, 6, LD>(g, L, GC, pos, lam, nu, A, P);
-    add_dag(wr, A, acc);
+    int p2[4];
+    opaque_start(pos, p2);
+    M3<T> A2 = A, P2 = P;
+    loop_steps<T, 2, SG, 3, 6, LD>(g, L, GC, p2, lam, nu, A2, P2);
+    add_dag(wr, A2, acc);
   }
+  loop_steps<T, 0, SG, 3, 4, LD>(g, L, GC, pos, lam, nu, A, P);  // S0: L N -L -N
+  add_dag(wp, A, acc);
 }
 
 template <typename T, bool OI>
