@@ -747,15 +747,20 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(part, 0, sizeof(double) * nparts, s));
 
-  // forward, keeping every c-th field and the staple sums of each segment's last step
+  // forward, keeping every c-th field and the staple sums of each segment's last step; the last
+  // segment's fields and staple sums go straight to the slots its recomputation would fill, so the
+  // adjoint starts on it without recomputing
   const void *cur = U->ptr;
+  const int k0_last = (nck - 1) * c;  // first step of the last segment
   {
     const Range range_("backward: forward smearing");
     for (int k = 0; k < n; k++) {
       if (k % c == 0) HIPCHK(hipMemcpyAsync(slot(k / c), cur, fb, hipMemcpyDeviceToDevice, s));
-      void *nxt = (cur == tmp0) ? tmp1 : tmp0;
+      const bool in_last = k >= k0_last && k < n - 1;
+      void *nxt = in_last ? slot((size_t)nck + (k - k0_last)) : (cur == tmp0 ? tmp1 : tmp0);
       const bool last = k % c == c - 1 || k == n - 1;
-      HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s, last ? clast(k / c) : nullptr));
+      void *cs = last ? clast(k / c) : in_last ? csum(k - k0_last) : nullptr;
+      HIPCHK(launch_smear_step<T>(g, cur, nxt, rho, eps, s, cs));
       cur = nxt;
     }
   }
@@ -771,7 +776,7 @@ mcg_status backward_impl(mcg_ctx *ctx, const mcg_field *U, double rho, double ep
     fields[0] = slot(seg);
     for (int j = 1; j < len; j++) {
       void *dst = slot(nck + j - 1);
-      HIPCHK(launch_smear_step<T>(g, fields[j - 1], dst, rho, eps, s, csum(j - 1)));
+      if (seg < nck - 1) HIPCHK(launch_smear_step<T>(g, fields[j - 1], dst, rho, eps, s, csum(j - 1)));
       fields[j] = dst;
     }
     for (int j = len - 1; j >= 0; j--) {
