@@ -14,8 +14,8 @@ __global__ __launch_bounds__(128) void k_smear(Geom g, const V2<T> *__restrict__
                                                V2<T> *__restrict__ Cst = nullptr) {
   // one block per (tile, direction, parity), the tiles as gather_site lays them out; the eight blocks
   // of a tile follow each other and each XCD takes a contiguous range of tiles (xcd_range), so the
-  // staple links that the eight share, and those of the neighbouring tiles along z and t, are still
-  // in that XCD's L2
+  // staple links that the eight share, and those of the neighbouring tiles along z and t, are mostly
+  // still in that XCD's L2
   const int w = xcd_range((int)blockIdx.x, (int)gridDim.x);
   const int h = gather_site(g, w >> 3, (int)threadIdx.x);
   if (h < 0) return;
