@@ -441,8 +441,10 @@ mcg_status mcg_wilson_loops(mcg_ctx *ctx, const mcg_field *U, int32_t nvec, cons
 /* L = R(S_n(U; rho, eps)^{G*}) at fixed G* (at a converged maximum this is
  * dL/dtheta of the fixed functional by the envelope theorem).  Returns the
  * ambient gradient gradU = dL/dRe U + i dL/dIm U (same layout and precision
- * as U) and host scalars L, dL/drho, dL/deps.  Smeared fields are
- * checkpointed every ckpt_every steps and recomputed between checkpoints.
+ * as U) and host scalars L, dL/drho, dL/deps, summed on the device in a
+ * fixed order (the same bits on every call).  Smeared fields are
+ * checkpointed every ckpt_every steps and recomputed between checkpoints,
+ * except the last segment's, which the forward pass keeps.
  * Device workspace held by the context: with c = ckpt_every (n if <= 0 or
  * > n) and m = (eps == 1 ? 1 : 2), ceil(n/c) * (1 + m) + (c - 1) * (1 + m) + 5
  * fields of U's size (the checkpoints, one segment's fields, and staple sums);
